@@ -1,0 +1,251 @@
+/*
+ * dpdlp.h -- C ABI of the single-GPU (MI355X, gfx950) restarted
+ * reflected-Halpern PDHG linear-programming solver (the PDLP family, as
+ * distributed by D-PDLP, arXiv 2601.07628).
+ *
+ * Problem (Sec. 2.1, problem (1)):
+ *     min  c^T x   s.t.   con_lo <= A x <= con_hi,   var_lo <= x <= var_hi
+ * with A given in CSR.  An '=' row has con_lo == con_hi, a '>=' row has
+ * con_hi == +inf, a '<=' row has con_lo == -inf; IEEE +-inf are the only
+ * infinities.  The dual variable y follows the sign convention
+ * L(x, y) = c^T x - y^T A x - p(-y; con_lo, con_hi): y >= 0 on '>=' rows,
+ * y <= 0 on '<=' rows, y = 0 on free rows (the sets Y_i of Sec. 2.1).
+ *
+ * Every call returns an int: DPDLP_OK (0) or a negative DPDLP_E_* code, with
+ * a message in dpdlp_last_error().  Not converging is not an error: it is
+ * reported in dpdlp_result.status.  All pointers are plain host or device
+ * pointers as stated per argument; "stream" is a hipStream_t passed as void*
+ * (NULL = the null stream).  One problem handle is used by one host thread
+ * and one stream at a time.
+ */
+#ifndef DPDLP_H
+#define DPDLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define DPDLP_OK               0
+#define DPDLP_E_INVALID_ARG   -1   /* a NULL pointer, a size out of range      */
+#define DPDLP_E_BAD_CSR       -2   /* row_ptr not monotone, column out of      */
+                                   /* range, duplicate (i,j), non-finite value */
+#define DPDLP_E_BAD_BOUNDS    -3   /* lo > hi, NaN, lo = +inf or hi = -inf     */
+#define DPDLP_E_HIP           -4   /* a HIP runtime call failed                */
+#define DPDLP_E_OOM           -5   /* device memory exhausted                  */
+#define DPDLP_E_NOT_SUPPORTED -6   /* a feature not built / wrong device       */
+
+/* ---- solve status (dpdlp_result.status) -------------------------------- */
+#define DPDLP_RUNNING          0
+#define DPDLP_CONVERGED        1   /* max(r_primal, r_dual, r_gap) <= eps      */
+#define DPDLP_ITER_LIMIT       2
+#define DPDLP_TIME_LIMIT       3
+#define DPDLP_NUMERICAL        4   /* a NaN/Inf appeared in the iterate        */
+
+#define DPDLP_MEM_HOST         0
+#define DPDLP_MEM_DEVICE       1
+
+#define DPDLP_FP64             0
+#define DPDLP_FP32_MIXED       1
+
+/* Input LP in CSR.  int32 indices: nnz < 2^31 (App. E.2 prices 4-byte
+ * indices).  Column indices may be unsorted inside a row; duplicates are
+ * rejected.  mem_kind says whether every pointer is host or device memory.
+ * The caller keeps ownership; dpdlp_problem_create deep-copies.           */
+typedef struct dpdlp_csr_lp {
+    int32_t m, n;                 /* rows, columns; both >= 1            */
+    const int32_t *row_ptr;       /* [m+1], row_ptr[0] = 0, monotone     */
+    const int32_t *col_idx;       /* [nnz], nnz = row_ptr[m]             */
+    const double *val;            /* [nnz]                               */
+    const double *c;              /* [n]                                 */
+    const double *con_lo, *con_hi;/* [m]                                 */
+    const double *var_lo, *var_hi;/* [n]                                 */
+    int32_t mem_kind;             /* DPDLP_MEM_HOST or DPDLP_MEM_DEVICE  */
+} dpdlp_csr_lp;
+
+/* Solver parameters; dpdlp_params_default() fills the defaults given here.
+ * The paper fixes none of the constants except the block size B = 256 of
+ * the block-wise permutation (Sec. 4.2); the rest follow PDLP practice.   */
+typedef struct dpdlp_params {
+    double eps;               /* 1e-8: relative KKT tolerance (App. B.4)     */
+    int64_t max_iters;        /* 100000                                      */
+    double time_limit;        /* seconds, <= 0: none                         */
+    int32_t check_period;     /* K = 64: KKT/restart check every K (App. D)  */
+    int32_t ruiz_iters;       /* 10 Ruiz infinity-norm passes                */
+    double gamma;             /* 1.0: reflection of the Halpern step (App. A)*/
+    double beta_suf, beta_nec, beta_art;   /* 0.2, 0.8, 0.36 (App. B.2)     */
+    double kp, ki, kd;        /* 0.99, 0.01, 0.0: PID gains (App. B.3)       */
+    double eta;               /* > 0: fixed step; 0: eta_safety/sigma_max(A~)*/
+    double omega0;            /* > 0: fixed initial primal weight; 0: ||c~||/||b~|| */
+    double eta_safety;        /* 0.998                                       */
+    int32_t power_max_iters;  /* 5000                                        */
+    int32_t use_pc;           /* 1: one Pock-Chambolle pass after Ruiz       */
+    double power_tol;         /* 1e-6: relative change that stops the power iteration */
+    double pc_alpha;          /* 1.0                                         */
+    int32_t perm_block;       /* 256: block size of the block-wise random    */
+                              /* permutation (Sec. 4.2); 0: no permutation   */
+    int32_t tile_nnz;         /* nonzeros per workgroup tile (Sec. 4.3 at CU */
+                              /* granularity); 0 = default 2048, max 2048    */
+    uint64_t perm_seed;       /* seed of the block permutation               */
+    int32_t precision;        /* DPDLP_FP64 or DPDLP_FP32_MIXED              */
+    int32_t xcd_remap;        /* 1: map consecutive tiles onto one XCD        */
+    double fp32_switch_tol;   /* FP32 -> FP64 switch when KKT <= this (1e-6) */
+    int32_t fp32_stall_checks;/* ... or no 2x KKT improvement in this many checks (8) */
+    int32_t pad0;
+} dpdlp_params;
+
+typedef struct dpdlp_result {
+    int32_t status;           /* DPDLP_CONVERGED, ... */
+    int32_t restarts;
+    int64_t iters;            /* PDHG iterations run (FP32 + FP64)           */
+    int64_t fp32_iters;       /* iterations run in FP32 (mixed mode)         */
+    double r_primal, r_dual, r_gap;   /* at the last check (App. B.4)        */
+    double obj_primal, obj_dual;
+    double omega, eta, sigma_max;
+    double setup_seconds, solve_seconds;
+    int32_t power_iters, n_checks;
+} dpdlp_result;
+
+/* Scalars of the iteration state, for checkpoint / resume and parity tests. */
+typedef struct dpdlp_state {
+    double omega, r0, r_prev, pid_int, pid_prev;
+    int64_t k, t;             /* epoch iteration, total iteration            */
+    int32_t pid_started, restarts, status, n_checks;
+    double r_primal, r_dual, r_gap, obj_primal, obj_dual, r_fixed_point;
+} dpdlp_state;
+
+/* One record per check (restart-decision log). restart: 0 none,
+ * 1 sufficient, 2 necessary, 3 artificial decay (App. B.2).               */
+typedef struct dpdlp_log_rec {
+    int64_t t, k;
+    double r, r0, r_primal, r_dual, r_gap, omega;
+    int32_t restart, pad;
+} dpdlp_log_rec;
+
+typedef struct dpdlp_problem dpdlp_problem;
+
+/* Default parameters (values above). */
+void dpdlp_params_default(dpdlp_params *p);
+
+/* Ingest and prepare a problem on the current HIP device, on `stream`:
+ * validate (host), block-wise random permutation of rows and columns
+ * (Sec. 4.2), CSC build (App. E.3 keeps both formats), nonzero-aware
+ * workgroup tiles (Sec. 4.3), Ruiz + Pock-Chambolle rescaling, the power
+ * iteration for eta and the initial primal weight.  *out receives a handle
+ * that owns every device buffer; free it with dpdlp_problem_destroy.
+ * Errors: INVALID_ARG, BAD_CSR, BAD_BOUNDS, HIP, OOM.                     */
+int dpdlp_problem_create(const dpdlp_csr_lp *lp, const dpdlp_params *params,
+                         void *stream, dpdlp_problem **out);
+int dpdlp_problem_destroy(dpdlp_problem *prob);
+
+/* Start from (x0, y0) (original space; NULL = zeros): the point is scaled,
+ * clamped into X and projected onto Y, and becomes the epoch anchor.  The
+ * pointers are host or device per mem_kind.                              */
+int dpdlp_init(dpdlp_problem *prob, const double *x0, const double *y0,
+               int32_t mem_kind, void *stream);
+
+/* Continue the restarted Halpern PDHG loop (Algorithm 1 at one device;
+ * App. A-B) for at most n_iters iterations, stopping early on convergence,
+ * the time limit, or max_iters in total.  Checks run every check_period
+ * iterations and at the first iteration of each epoch.                    */
+int dpdlp_iterate(dpdlp_problem *prob, int64_t n_iters, void *stream);
+
+/* Full solve: dpdlp_init + dpdlp_iterate(max_iters) + output.  x_out [n] and
+ * y_out [m] (may be NULL) receive T(z) of the last iteration in the original
+ * space and order.  Pointers are host or device per mem_kind.  info may be
+ * NULL.                                                                  */
+int dpdlp_solve(dpdlp_problem *prob, const double *x0, const double *y0,
+                double *x_out, double *y_out, int32_t mem_kind,
+                dpdlp_result *info, void *stream);
+
+/* Result of the work done so far, and the current primal/dual point T(z)
+ * in the original space and order (x_out/y_out may be NULL).              */
+int dpdlp_get_result(dpdlp_problem *prob, double *x_out, double *y_out,
+                     int32_t mem_kind, dpdlp_result *info, void *stream);
+
+/* Export / import the full iteration state in the SCALED space, original
+ * order: the Halpern iterate (x, y), the epoch anchor (xa, ya), the last
+ * T(z) (xh, yh), plus the scalars.  Any array pointer may be NULL on export.
+ * Host or device per mem_kind.  Import then dpdlp_iterate continues exactly
+ * as an uninterrupted run would.                                          */
+int dpdlp_state_export(dpdlp_problem *prob, dpdlp_state *st, double *x, double *y,
+                       double *xa, double *ya, double *xh, double *yh,
+                       int32_t mem_kind, void *stream);
+int dpdlp_state_import(dpdlp_problem *prob, const dpdlp_state *st, const double *x,
+                       const double *y, const double *xa, const double *ya,
+                       const double *xh, const double *yh, int32_t mem_kind,
+                       void *stream);
+
+/* Copy out the restart-decision log (up to cap records, oldest first);
+ * *count receives the number of records available.                       */
+int dpdlp_get_log(dpdlp_problem *prob, dpdlp_log_rec *recs, int32_t cap, int32_t *count);
+
+/* Products with the SCALED matrix A~ in the original order: out = A~ in
+ * (transpose = 0; in [n], out [m]) or A~^T in (transpose = 1).  Device
+ * pointers.  Used by tests and the standalone SpMV bandwidth benchmark.   */
+int dpdlp_spmv(dpdlp_problem *prob, int32_t transpose, const double *in, double *out,
+               void *stream);
+
+/* KKT of the original problem at an original-space point (x, y) with primal
+ * step tau (tau <= 0: the current eta/omega) (App. B.4).  out5 (host):
+ * r_primal, r_dual, r_gap, obj_primal, obj_dual.  x, y per mem_kind.       */
+int dpdlp_kkt(dpdlp_problem *prob, const double *x, const double *y, double tau,
+              int32_t mem_kind, double *out5, void *stream);
+
+/* Scaling vectors D_r [m], D_c [n] (A~ = D_r A D_c) in the original order,
+ * eta, sigma_max and omega0 (host pointers; any may be NULL).             */
+int dpdlp_get_scaling(dpdlp_problem *prob, double *dr, double *dc, double *eta,
+                      double *sigma_max, double *omega0, void *stream);
+
+/* Time one kernel class over `reps` launches on `stream` with HIP events:
+ * which = 0 fused primal step, 1 fused dual step, 2 CSR SpMV, 3 CSC SpMV.
+ * *avg_ms receives the mean duration; *bytes the algorithmic bytes moved per
+ * launch (matrix stream + vector reads and writes, gathered vectors once).
+ * Advances no solver state (the steps run on scratch copies of x and y).  */
+int dpdlp_time_kernel(dpdlp_problem *prob, int32_t which, int32_t reps, void *stream,
+                      double *avg_ms, double *bytes);
+
+/* Per-kernel timing with HIP events recorded on the solver's stream around
+ * every launch of dpdlp_iterate.  enable = 1 clears the totals and starts
+ * recording; 0 stops.  dpdlp_get_profile fills, per kernel class c
+ * (0 fused primal step, 1 fused dual step, 2 CSR check pass, 3 CSC check
+ * pass, 4 control kernel, 5-7 unused), the summed milliseconds, the launch
+ * count and the algorithmic bytes one launch moves (matrix stream once,
+ * every vector read or written once, gathered vectors once).  Arrays have 8
+ * entries (host); any may be NULL.                                        */
+int dpdlp_profile_enable(dpdlp_problem *prob, int32_t enable);
+int dpdlp_get_profile(dpdlp_problem *prob, double *total_ms, int64_t *launches,
+                      double *bytes_per_launch);
+
+/* ---- host-only preprocessing, callable without a GPU -------------------- */
+
+/* Validate a host CSR LP; 0 or BAD_CSR / BAD_BOUNDS / INVALID_ARG.        */
+int dpdlp_validate(const dpdlp_csr_lp *lp);
+
+/* Block-wise random permutation (Sec. 4.2): split [0, count) into blocks of
+ * `block` (last one partial), shuffle the blocks with a seeded Fisher-Yates
+ * (splitmix64 stream), keep the order inside each block.  perm[new] = old.
+ * block <= 0 gives the identity.                                          */
+int dpdlp_block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t *perm);
+
+/* Nonzero-aware tiles over segment pointers seg_ptr[nseg+1] (Sec. 4.3 at
+ * workgroup granularity): consecutive segments are packed while the tile
+ * holds <= tile_nnz nonzeros and <= 1024 segments; a segment longer than
+ * tile_nnz is split into pieces of tile_nnz.  tiles[8*i .. 8*i+7] =
+ * {seg_begin, seg_end, nnz_begin, nnz_end, width_log2, piece, npieces, 0}.
+ * Call with tiles = NULL to get the count in *ntiles, then again with room
+ * for that many.                                                          */
+int dpdlp_build_tiles(const int32_t *seg_ptr, int32_t nseg, int32_t tile_nnz,
+                      int32_t *tiles, int32_t *ntiles);
+
+/* Messages. */
+const char *dpdlp_status_string(int32_t status);
+const char *dpdlp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPDLP_H */

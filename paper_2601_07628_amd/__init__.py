@@ -1,0 +1,373 @@
+"""Python binding of libdpdlp (the single-GPU restarted Halpern PDHG solver).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels on the GPU.  The functions keep the C names of ``include/dpdlp.h``;
+``Problem`` is a small convenience wrapper over them.  PyTorch is used only
+for device memory and streams, and only when the caller passes tensors.
+
+Loading fails loudly (ImportError) when ``libdpdlp.so`` has not been built;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpdlp.so")
+
+OK = 0
+E_INVALID_ARG, E_BAD_CSR, E_BAD_BOUNDS, E_HIP, E_OOM, E_NOT_SUPPORTED = -1, -2, -3, -4, -5, -6
+RUNNING, CONVERGED, ITER_LIMIT, TIME_LIMIT, NUMERICAL = 0, 1, 2, 3, 4
+MEM_HOST, MEM_DEVICE = 0, 1
+FP64, FP32_MIXED = 0, 1
+KERNEL_CLASSES = ("primal", "dual", "check_csr", "check_csc", "control")
+
+
+class DpdlpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dpdlp error {code}: {msg}")
+        self.code = code
+
+
+class CsrLP(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p), ("c", C.c_void_p),
+                ("con_lo", C.c_void_p), ("con_hi", C.c_void_p),
+                ("var_lo", C.c_void_p), ("var_hi", C.c_void_p),
+                ("mem_kind", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("eps", C.c_double), ("max_iters", C.c_int64),
+                ("time_limit", C.c_double), ("check_period", C.c_int32),
+                ("ruiz_iters", C.c_int32), ("gamma", C.c_double),
+                ("beta_suf", C.c_double), ("beta_nec", C.c_double),
+                ("beta_art", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
+                ("kd", C.c_double), ("eta", C.c_double), ("omega0", C.c_double),
+                ("eta_safety", C.c_double), ("power_max_iters", C.c_int32),
+                ("use_pc", C.c_int32), ("power_tol", C.c_double),
+                ("pc_alpha", C.c_double), ("perm_block", C.c_int32),
+                ("tile_nnz", C.c_int32), ("perm_seed", C.c_uint64),
+                ("precision", C.c_int32), ("xcd_remap", C.c_int32),
+                ("fp32_switch_tol", C.c_double), ("fp32_stall_checks", C.c_int32),
+                ("pad0", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("restarts", C.c_int32),
+                ("iters", C.c_int64), ("fp32_iters", C.c_int64),
+                ("r_primal", C.c_double), ("r_dual", C.c_double),
+                ("r_gap", C.c_double), ("obj_primal", C.c_double),
+                ("obj_dual", C.c_double), ("omega", C.c_double),
+                ("eta", C.c_double), ("sigma_max", C.c_double),
+                ("setup_seconds", C.c_double), ("solve_seconds", C.c_double),
+                ("power_iters", C.c_int32), ("n_checks", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class State(C.Structure):
+    _fields_ = [("omega", C.c_double), ("r0", C.c_double), ("r_prev", C.c_double),
+                ("pid_int", C.c_double), ("pid_prev", C.c_double),
+                ("k", C.c_int64), ("t", C.c_int64), ("pid_started", C.c_int32),
+                ("restarts", C.c_int32), ("status", C.c_int32),
+                ("n_checks", C.c_int32), ("r_primal", C.c_double),
+                ("r_dual", C.c_double), ("r_gap", C.c_double),
+                ("obj_primal", C.c_double), ("obj_dual", C.c_double),
+                ("r_fixed_point", C.c_double)]
+
+
+class LogRec(C.Structure):
+    _fields_ = [("t", C.c_int64), ("k", C.c_int64), ("r", C.c_double),
+                ("r0", C.c_double), ("r_primal", C.c_double),
+                ("r_dual", C.c_double), ("r_gap", C.c_double),
+                ("omega", C.c_double), ("restart", C.c_int32), ("pad", C.c_int32)]
+
+
+# Every symbol include/dpdlp.h declares (checked by the CPU test suite).
+EXPORTS = (
+    "dpdlp_params_default", "dpdlp_problem_create", "dpdlp_problem_destroy",
+    "dpdlp_init", "dpdlp_iterate", "dpdlp_solve", "dpdlp_get_result",
+    "dpdlp_state_export", "dpdlp_state_import", "dpdlp_get_log", "dpdlp_spmv",
+    "dpdlp_kkt", "dpdlp_get_scaling", "dpdlp_time_kernel",
+    "dpdlp_profile_enable", "dpdlp_get_profile", "dpdlp_validate",
+    "dpdlp_block_permutation", "dpdlp_build_tiles", "dpdlp_status_string",
+    "dpdlp_last_error",
+)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python paper_2601_07628_amd/build.py` (there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    sig = {
+        "dpdlp_params_default": ([C.POINTER(Params)], None),
+        "dpdlp_problem_create": ([C.POINTER(CsrLP), C.POINTER(Params), vp, C.POINTER(vp)], C.c_int),
+        "dpdlp_problem_destroy": ([vp], C.c_int),
+        "dpdlp_init": ([vp, vp, vp, i32, vp], C.c_int),
+        "dpdlp_iterate": ([vp, i64, vp], C.c_int),
+        "dpdlp_solve": ([vp, vp, vp, vp, vp, i32, C.POINTER(Result), vp], C.c_int),
+        "dpdlp_get_result": ([vp, vp, vp, i32, C.POINTER(Result), vp], C.c_int),
+        "dpdlp_state_export": ([vp, C.POINTER(State), vp, vp, vp, vp, vp, vp, i32, vp], C.c_int),
+        "dpdlp_state_import": ([vp, C.POINTER(State), vp, vp, vp, vp, vp, vp, i32, vp], C.c_int),
+        "dpdlp_get_log": ([vp, vp, i32, C.POINTER(i32)], C.c_int),
+        "dpdlp_spmv": ([vp, i32, vp, vp, vp], C.c_int),
+        "dpdlp_kkt": ([vp, vp, vp, dbl, i32, vp, vp], C.c_int),
+        "dpdlp_get_scaling": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
+        "dpdlp_time_kernel": ([vp, i32, i32, vp, vp, vp], C.c_int),
+        "dpdlp_profile_enable": ([vp, i32], C.c_int),
+        "dpdlp_get_profile": ([vp, vp, vp, vp], C.c_int),
+        "dpdlp_validate": ([C.POINTER(CsrLP)], C.c_int),
+        "dpdlp_block_permutation": ([i32, i32, u64, vp], C.c_int),
+        "dpdlp_build_tiles": ([vp, i32, i32, vp, C.POINTER(i32)], C.c_int),
+        "dpdlp_status_string": ([i32], C.c_char_p),
+        "dpdlp_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise DpdlpError(rc, _lib.dpdlp_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    """Plain address of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()                  # torch.Tensor
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream            # torch.cuda.Stream
+
+
+# ---- same-name functions (marshalling only) --------------------------------
+def dpdlp_params_default() -> Params:
+    p = Params()
+    _lib.dpdlp_params_default(C.byref(p))
+    return p
+
+
+def dpdlp_status_string(status: int) -> str:
+    return _lib.dpdlp_status_string(status).decode()
+
+
+def dpdlp_last_error() -> str:
+    return _lib.dpdlp_last_error().decode()
+
+
+def _csr_struct(arrays, m, n, mem_kind):
+    return CsrLP(m, n, *[_ptr(arrays[k]) for k in (
+        "row_ptr", "col_idx", "val", "c", "con_lo", "con_hi", "var_lo", "var_hi")],
+        mem_kind)
+
+
+def host_arrays(lp) -> dict:
+    """Contiguous host arrays (int32 / float64) of an LP-like object."""
+    return dict(
+        row_ptr=np.ascontiguousarray(lp.row_ptr, np.int32),
+        col_idx=np.ascontiguousarray(lp.col_idx, np.int32),
+        val=np.ascontiguousarray(lp.val, np.float64),
+        c=np.ascontiguousarray(lp.c, np.float64),
+        con_lo=np.ascontiguousarray(lp.con_lo, np.float64),
+        con_hi=np.ascontiguousarray(lp.con_hi, np.float64),
+        var_lo=np.ascontiguousarray(lp.var_lo, np.float64),
+        var_hi=np.ascontiguousarray(lp.var_hi, np.float64))
+
+
+def dpdlp_validate(lp) -> int:
+    """Host-side validation (no GPU needed); returns the C return code."""
+    a = host_arrays(lp)
+    s = _csr_struct(a, int(lp.m), int(lp.n), MEM_HOST)
+    return int(_lib.dpdlp_validate(C.byref(s)))
+
+
+def dpdlp_block_permutation(count: int, block: int, seed: int) -> np.ndarray:
+    perm = np.zeros(max(count, 1), np.int32)
+    _check(_lib.dpdlp_block_permutation(count, block, seed, _ptr(perm)))
+    return perm[:count]
+
+
+def dpdlp_build_tiles(seg_ptr, tile_nnz: int = 0) -> np.ndarray:
+    """Nonzero-aware tiles; rows of {seg_begin, seg_end, nnz_begin, nnz_end,
+    width_log2, piece, npieces, 0}."""
+    sp_ = np.ascontiguousarray(seg_ptr, np.int32)
+    cnt = C.c_int32(0)
+    _check(_lib.dpdlp_build_tiles(_ptr(sp_), sp_.size - 1, tile_nnz, None, C.byref(cnt)))
+    out = np.zeros((max(cnt.value, 1), 8), np.int32)
+    cnt2 = C.c_int32(cnt.value)
+    _check(_lib.dpdlp_build_tiles(_ptr(sp_), sp_.size - 1, tile_nnz, _ptr(out), C.byref(cnt2)))
+    return out[: cnt.value]
+
+
+def dpdlp_problem_create(lp, params: Optional[Params] = None, stream=None,
+                         device_arrays: Optional[dict] = None):
+    """Create a problem handle from an LP-like object (host arrays) or from a
+    dict of device tensors (``device_arrays``, same keys as host_arrays)."""
+    if device_arrays is not None:
+        keep = device_arrays
+        s = _csr_struct(keep, int(lp.m), int(lp.n), MEM_DEVICE)
+    else:
+        keep = host_arrays(lp)
+        s = _csr_struct(keep, int(lp.m), int(lp.n), MEM_HOST)
+    h = C.c_void_p()
+    prm = params if params is not None else dpdlp_params_default()
+    _check(_lib.dpdlp_problem_create(C.byref(s), C.byref(prm), _stream(stream), C.byref(h)))
+    return h
+
+
+def dpdlp_problem_destroy(h):
+    return _check(_lib.dpdlp_problem_destroy(h))
+
+
+# ---- convenience wrapper ------------------------------------------------------
+class Problem:
+    """A prepared problem on the current GPU (owns the library handle)."""
+
+    def __init__(self, lp, params: Optional[Params] = None, stream=None, **kw):
+        prm = params if params is not None else dpdlp_params_default()
+        for k, v in kw.items():
+            if not hasattr(prm, k):
+                raise AttributeError(f"no parameter {k}")
+            setattr(prm, k, v)
+        self.params = prm
+        self.m, self.n = int(lp.m), int(lp.n)
+        self.stream = stream
+        self.h = dpdlp_problem_create(lp, prm, stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            _lib.dpdlp_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _s(self):
+        return _stream(self.stream)
+
+    def init(self, x0=None, y0=None):
+        x0 = None if x0 is None else np.ascontiguousarray(x0, np.float64)
+        y0 = None if y0 is None else np.ascontiguousarray(y0, np.float64)
+        _check(_lib.dpdlp_init(self.h, _ptr(x0), _ptr(y0), MEM_HOST, self._s))
+
+    def iterate(self, n_iters: int):
+        _check(_lib.dpdlp_iterate(self.h, int(n_iters), self._s))
+
+    def result(self, want_xy: bool = True) -> dict:
+        r = Result()
+        x = np.zeros(self.n) if want_xy else None
+        y = np.zeros(self.m) if want_xy else None
+        _check(_lib.dpdlp_get_result(self.h, _ptr(x), _ptr(y), MEM_HOST, C.byref(r), self._s))
+        d = r.as_dict()
+        d["x"], d["y"] = x, y
+        return d
+
+    def solve(self, x0=None, y0=None) -> dict:
+        r = Result()
+        x, y = np.zeros(self.n), np.zeros(self.m)
+        x0 = None if x0 is None else np.ascontiguousarray(x0, np.float64)
+        y0 = None if y0 is None else np.ascontiguousarray(y0, np.float64)
+        _check(_lib.dpdlp_solve(self.h, _ptr(x0), _ptr(y0), _ptr(x), _ptr(y), MEM_HOST,
+                                C.byref(r), self._s))
+        d = r.as_dict()
+        d["x"], d["y"] = x, y
+        return d
+
+    def state(self) -> dict:
+        st = State()
+        arrs = {k: np.zeros(self.n if k.startswith("x") else self.m)
+                for k in ("x", "y", "xa", "ya", "xh", "yh")}
+        _check(_lib.dpdlp_state_export(self.h, C.byref(st), *[_ptr(arrs[k]) for k in (
+            "x", "y", "xa", "ya", "xh", "yh")], MEM_HOST, self._s))
+        arrs["scalars"] = {k: getattr(st, k) for k, _ in st._fields_}
+        arrs["_state"] = st
+        return arrs
+
+    def load_state(self, s: dict):
+        st = s["_state"]
+        _check(_lib.dpdlp_state_import(self.h, C.byref(st), *[
+            _ptr(np.ascontiguousarray(s[k], np.float64)) for k in (
+                "x", "y", "xa", "ya", "xh", "yh")], MEM_HOST, self._s))
+
+    def log(self) -> list:
+        cnt = C.c_int32(0)
+        _check(_lib.dpdlp_get_log(self.h, None, 0, C.byref(cnt)))
+        recs = (LogRec * max(cnt.value, 1))()
+        _check(_lib.dpdlp_get_log(self.h, C.cast(recs, C.c_void_p), cnt.value, C.byref(cnt)))
+        return [dict(t=r.t, k=r.k, r=r.r, r0=r.r0, r_primal=r.r_primal, r_dual=r.r_dual,
+                     r_gap=r.r_gap, omega=r.omega, restart=r.restart)
+                for r in (recs[i] for i in range(cnt.value))]
+
+    def spmv(self, vec, transpose=False):
+        """A~ v or A~^T v on device tensors (torch), original order."""
+        import torch
+        out = torch.empty(self.n if transpose else self.m, dtype=torch.float64,
+                          device=vec.device)
+        _check(_lib.dpdlp_spmv(self.h, int(transpose), _ptr(vec), _ptr(out), self._s))
+        return out
+
+    def kkt(self, x, y, tau: float = 0.0):
+        out = np.zeros(5)
+        _check(_lib.dpdlp_kkt(self.h, _ptr(np.ascontiguousarray(x, np.float64)),
+                              _ptr(np.ascontiguousarray(y, np.float64)), float(tau),
+                              MEM_HOST, _ptr(out), self._s))
+        return out
+
+    def scaling(self):
+        dr, dc = np.zeros(self.m), np.zeros(self.n)
+        eta, smax, w0 = C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.dpdlp_get_scaling(self.h, _ptr(dr), _ptr(dc), C.byref(eta),
+                                      C.byref(smax), C.byref(w0), self._s))
+        return dict(dr=dr, dc=dc, eta=eta.value, sigma_max=smax.value, omega0=w0.value)
+
+    def time_kernel(self, which: int, reps: int = 20):
+        ms, by = C.c_double(), C.c_double()
+        _check(_lib.dpdlp_time_kernel(self.h, which, reps, self._s, C.byref(ms), C.byref(by)))
+        return ms.value, by.value
+
+    def profile_enable(self, on: bool = True):
+        _check(_lib.dpdlp_profile_enable(self.h, int(on)))
+
+    def profile(self) -> dict:
+        ms = np.zeros(8)
+        n = np.zeros(8, np.int64)
+        b = np.zeros(8)
+        _check(_lib.dpdlp_get_profile(self.h, _ptr(ms), _ptr(n), _ptr(b)))
+        return {name: dict(total_ms=float(ms[i]), launches=int(n[i]),
+                           bytes_per_launch=float(b[i]))
+                for i, name in enumerate(KERNEL_CLASSES)}

@@ -1,0 +1,310 @@
+// Host preprocessing of the LP: validation, the block-wise random
+// permutation (Sec. 4.2 of the D-PDLP paper), the CSC copy (both formats are
+// kept so that A^T y needs no atomics, App. E.3) and the nonzero-aware tiles
+// that balance nonzeros across workgroups (Sec. 4.3, applied at workgroup
+// instead of GPU granularity).  Integer work only; no GPU calls.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "dpdlp_internal.h"
+
+namespace dpdlp {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+int validate_host(const dpdlp_csr_lp *lp)
+{
+    if (!lp) { set_error("lp is NULL"); return DPDLP_E_INVALID_ARG; }
+    if (lp->m < 1 || lp->n < 1) {
+        set_error("m and n must be >= 1");
+        return DPDLP_E_INVALID_ARG;
+    }
+    if (!lp->row_ptr || !lp->c || !lp->con_lo || !lp->con_hi || !lp->var_lo ||
+        !lp->var_hi) {
+        set_error("a required array is NULL");
+        return DPDLP_E_INVALID_ARG;
+    }
+    const int32_t m = lp->m, n = lp->n;
+    if (lp->row_ptr[0] != 0) { set_error("row_ptr[0] != 0"); return DPDLP_E_BAD_CSR; }
+    for (int32_t i = 0; i < m; ++i)
+        if (lp->row_ptr[i + 1] < lp->row_ptr[i]) {
+            set_error("row_ptr not monotone at row " + std::to_string(i));
+            return DPDLP_E_BAD_CSR;
+        }
+    const int64_t nnz = lp->row_ptr[m];
+    if (nnz > 0 && (!lp->col_idx || !lp->val)) {
+        set_error("col_idx / val is NULL");
+        return DPDLP_E_INVALID_ARG;
+    }
+    std::vector<int32_t> mark((size_t)n, -1);
+    for (int32_t i = 0; i < m; ++i)
+        for (int64_t p = lp->row_ptr[i]; p < lp->row_ptr[i + 1]; ++p) {
+            int32_t j = lp->col_idx[p];
+            if (j < 0 || j >= n) {
+                set_error("column index out of range at nonzero " + std::to_string(p));
+                return DPDLP_E_BAD_CSR;
+            }
+            if (mark[(size_t)j] == i) {
+                set_error("duplicate entry (" + std::to_string(i) + "," +
+                          std::to_string(j) + ")");
+                return DPDLP_E_BAD_CSR;
+            }
+            mark[(size_t)j] = i;
+            if (!std::isfinite(lp->val[p])) {
+                set_error("non-finite matrix value at nonzero " + std::to_string(p));
+                return DPDLP_E_BAD_CSR;
+            }
+        }
+    for (int32_t j = 0; j < n; ++j) {
+        if (!std::isfinite(lp->c[j])) {
+            set_error("non-finite c[" + std::to_string(j) + "]");
+            return DPDLP_E_BAD_BOUNDS;
+        }
+        double lo = lp->var_lo[j], hi = lp->var_hi[j];
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi || lo == INFINITY ||
+            hi == -INFINITY) {
+            set_error("bad variable bounds at column " + std::to_string(j));
+            return DPDLP_E_BAD_BOUNDS;
+        }
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        double lo = lp->con_lo[i], hi = lp->con_hi[i];
+        if (std::isnan(lo) || std::isnan(hi) || lo > hi || lo == INFINITY ||
+            hi == -INFINITY) {
+            set_error("bad constraint bounds at row " + std::to_string(i));
+            return DPDLP_E_BAD_BOUNDS;
+        }
+    }
+    return DPDLP_OK;
+}
+
+// splitmix64: a small published counter-based generator (Steele, Lea, Flood).
+static inline uint64_t splitmix64(uint64_t &s)
+{
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t *perm)
+{
+    if (block <= 0 || count <= block) {
+        for (int32_t i = 0; i < count; ++i) perm[i] = i;
+        return;
+    }
+    const int32_t nb = (count + block - 1) / block;
+    std::vector<int32_t> order((size_t)nb);
+    for (int32_t b = 0; b < nb; ++b) order[(size_t)b] = b;
+    uint64_t s = seed;
+    for (int32_t b = nb - 1; b > 0; --b) {      // Fisher-Yates over blocks
+        uint64_t r = splitmix64(s) % (uint64_t)(b + 1);
+        std::swap(order[(size_t)b], order[(size_t)r]);
+    }
+    int32_t pos = 0;
+    for (int32_t q = 0; q < nb; ++q) {
+        int32_t b = order[(size_t)q];
+        int32_t lo = b * block, hi = std::min(count, lo + block);
+        for (int32_t i = lo; i < hi; ++i) perm[pos++] = i;
+    }
+}
+
+static int32_t ceil_log2(int32_t v)
+{
+    int32_t l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+void build_tiles(const int32_t *ptr, int32_t nseg, int32_t tile_nnz,
+                 std::vector<Tile> &out)
+{
+    out.clear();
+    if (tile_nnz <= 0 || tile_nnz > kTileNnzMax) tile_nnz = kTileNnzMax;
+    int32_t s = 0;
+    while (s < nseg) {
+        int32_t len = ptr[s + 1] - ptr[s];
+        if (len > tile_nnz) {                      // long segment: split it
+            int32_t np = (len + tile_nnz - 1) / tile_nnz;
+            for (int32_t pc = 0; pc < np; ++pc) {
+                Tile t{};
+                t.seg_begin = s; t.seg_end = s + 1;
+                t.nnz_begin = ptr[s] + pc * tile_nnz;
+                t.nnz_end = std::min(ptr[s + 1], t.nnz_begin + tile_nnz);
+                t.width_log2 = 6; t.piece = pc; t.npieces = np;
+                out.push_back(t);
+            }
+            ++s;
+            continue;
+        }
+        int32_t start = s, nz = 0;
+        while (s < nseg && s - start < kMaxSegs) {
+            int32_t l = ptr[s + 1] - ptr[s];
+            if (l > tile_nnz || nz + l > tile_nnz) break;
+            nz += l;
+            ++s;
+        }
+        Tile t{};
+        t.seg_begin = start; t.seg_end = s;
+        t.nnz_begin = ptr[start]; t.nnz_end = ptr[s];
+        int32_t nsg = s - start;
+        int32_t avg = (nz + nsg - 1) / nsg;
+        t.width_log2 = std::min(6, ceil_log2(std::max(1, avg)));
+        t.piece = 0; t.npieces = 0;
+        out.push_back(t);
+    }
+}
+
+void permute_and_transpose(const dpdlp_csr_lp *lp, int32_t block, uint64_t seed,
+                           HostMatrix &H)
+{
+    const int32_t m = lp->m, n = lp->n;
+    H.m = m; H.n = n;
+    H.nnz = lp->row_ptr[m];
+    H.perm_row.resize((size_t)m);
+    H.perm_col.resize((size_t)n);
+    block_permutation(m, block, seed, H.perm_row.data());
+    block_permutation(n, block, seed ^ 0xC01D5EEDull, H.perm_col.data());
+    std::vector<int32_t> inv_col((size_t)n);
+    for (int32_t j = 0; j < n; ++j) inv_col[(size_t)H.perm_col[(size_t)j]] = j;
+
+    H.rp.assign((size_t)m + 1, 0);
+    for (int32_t i = 0; i < m; ++i) {
+        int32_t o = H.perm_row[(size_t)i];
+        H.rp[(size_t)i + 1] = H.rp[(size_t)i] + (lp->row_ptr[o + 1] - lp->row_ptr[o]);
+    }
+    H.ci.resize((size_t)H.nnz);
+    H.v.resize((size_t)H.nnz);
+    // rows are independent: fill them in parallel on the host
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto fill = [&](int32_t i0, int32_t i1) {
+        for (int32_t i = i0; i < i1; ++i) {
+            int32_t o = H.perm_row[(size_t)i];
+            int64_t src = lp->row_ptr[o], dst = H.rp[(size_t)i];
+            int32_t len = lp->row_ptr[o + 1] - lp->row_ptr[o];
+            for (int32_t q = 0; q < len; ++q) {
+                H.ci[(size_t)(dst + q)] = inv_col[(size_t)lp->col_idx[src + q]];
+                H.v[(size_t)(dst + q)] = lp->val[src + q];
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    int32_t chunk = (m + (int32_t)nth - 1) / (int32_t)nth;
+    for (unsigned q = 0; q < nth; ++q) {
+        int32_t a = (int32_t)q * chunk, b = std::min(m, a + chunk);
+        if (a < b) th.emplace_back(fill, a, b);
+    }
+    for (auto &t : th) t.join();
+
+    // CSC by counting, prefix sum and a stable scatter (row order kept).
+    H.cp.assign((size_t)n + 1, 0);
+    for (int64_t p = 0; p < H.nnz; ++p) H.cp[(size_t)H.ci[(size_t)p] + 1]++;
+    for (int32_t j = 0; j < n; ++j) H.cp[(size_t)j + 1] += H.cp[(size_t)j];
+    std::vector<int32_t> next(H.cp.begin(), H.cp.end() - 1);
+    H.ri.resize((size_t)H.nnz);
+    H.vt.resize((size_t)H.nnz);
+    for (int32_t i = 0; i < m; ++i)
+        for (int32_t p = H.rp[(size_t)i]; p < H.rp[(size_t)i + 1]; ++p) {
+            int32_t q = next[(size_t)H.ci[(size_t)p]]++;
+            H.ri[(size_t)q] = i;
+            H.vt[(size_t)q] = H.v[(size_t)p];
+        }
+}
+
+}  // namespace dpdlp
+
+using namespace dpdlp;
+
+extern "C" {
+
+const char *dpdlp_last_error(void) { return g_err.c_str(); }
+
+int dpdlp_validate(const dpdlp_csr_lp *lp)
+{
+    if (lp && lp->mem_kind != DPDLP_MEM_HOST) {
+        set_error("dpdlp_validate takes host pointers");
+        return DPDLP_E_INVALID_ARG;
+    }
+    return validate_host(lp);
+}
+
+int dpdlp_block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t *perm)
+{
+    if (count < 0 || (count > 0 && !perm)) {
+        set_error("bad arguments");
+        return DPDLP_E_INVALID_ARG;
+    }
+    block_permutation(count, block, seed, perm);
+    return DPDLP_OK;
+}
+
+int dpdlp_build_tiles(const int32_t *seg_ptr, int32_t nseg, int32_t tile_nnz,
+                      int32_t *tiles, int32_t *ntiles)
+{
+    if (!seg_ptr || nseg < 0 || !ntiles) {
+        set_error("bad arguments");
+        return DPDLP_E_INVALID_ARG;
+    }
+    std::vector<Tile> t;
+    build_tiles(seg_ptr, nseg, tile_nnz, t);
+    if (tiles) {
+        if (*ntiles < (int32_t)t.size()) {
+            set_error("tile buffer too small");
+            return DPDLP_E_INVALID_ARG;
+        }
+        std::memcpy(tiles, t.data(), t.size() * sizeof(Tile));
+    }
+    *ntiles = (int32_t)t.size();
+    return DPDLP_OK;
+}
+
+void dpdlp_params_default(dpdlp_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->eps = 1e-8;
+    p->max_iters = 100000;
+    p->time_limit = 0.0;
+    p->check_period = 64;
+    p->ruiz_iters = 10;
+    p->gamma = 1.0;
+    p->beta_suf = 0.2; p->beta_nec = 0.8; p->beta_art = 0.36;
+    p->kp = 0.99; p->ki = 0.01; p->kd = 0.0;
+    p->eta = 0.0; p->omega0 = 0.0; p->eta_safety = 0.998;
+    p->power_max_iters = 5000;
+    p->use_pc = 1;
+    p->power_tol = 1e-6;
+    p->pc_alpha = 1.0;
+    p->perm_block = 256;
+    p->tile_nnz = 0;
+    p->perm_seed = 20260107ull;
+    p->precision = DPDLP_FP64;
+    p->xcd_remap = 1;
+    p->fp32_switch_tol = 1e-6;
+    p->fp32_stall_checks = 8;
+}
+
+const char *dpdlp_status_string(int32_t s)
+{
+    switch (s) {
+    case DPDLP_RUNNING: return "running";
+    case DPDLP_CONVERGED: return "converged";
+    case DPDLP_ITER_LIMIT: return "iteration limit";
+    case DPDLP_TIME_LIMIT: return "time limit";
+    case DPDLP_NUMERICAL: return "numerical error";
+    case DPDLP_E_INVALID_ARG: return "invalid argument";
+    case DPDLP_E_BAD_CSR: return "bad CSR";
+    case DPDLP_E_BAD_BOUNDS: return "bad bounds";
+    case DPDLP_E_HIP: return "HIP error";
+    case DPDLP_E_OOM: return "out of device memory";
+    case DPDLP_E_NOT_SUPPORTED: return "not supported";
+    default: return "unknown";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+// Internal declarations shared by the host preprocessing (dpdlp_host.cpp)
+// and the device solver (dpdlp_solver.hip).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dpdlp.h"
+
+namespace dpdlp {
+
+// Tile descriptor: 8 int32 (see dpdlp_build_tiles).
+struct Tile {
+    int32_t seg_begin, seg_end, nnz_begin, nnz_end;
+    int32_t width_log2, piece, npieces, pad;
+};
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kTileNnzMax = 2048;    // products staged in LDS per tile
+constexpr int kMaxSegs = 1024;       // segments per tile
+
+void set_error(const std::string &msg);
+
+// Host copy of an LP after the block permutation, with both formats.
+struct HostMatrix {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    std::vector<int32_t> rp, ci;      // CSR (permuted)
+    std::vector<double> v;
+    std::vector<int32_t> cp, ri;      // CSC (permuted), row order kept
+    std::vector<double> vt;
+    std::vector<int32_t> perm_row, perm_col;   // perm[new] = old
+};
+
+int validate_host(const dpdlp_csr_lp *lp);
+void block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t *perm);
+void build_tiles(const int32_t *seg_ptr, int32_t nseg, int32_t tile_nnz,
+                 std::vector<Tile> &out);
+// Permute rows/columns of a host CSR LP and build the CSC copy.
+void permute_and_transpose(const dpdlp_csr_lp *lp, int32_t block, uint64_t seed,
+                           HostMatrix &H);
+
+}  // namespace dpdlp

@@ -1,0 +1,419 @@
+// Device kernels of the single-GPU restarted reflected-Halpern PDHG solver,
+// written for gfx950 (MI355X): wave64, 256-thread workgroups, LDS-staged
+// nonzero tiles, deterministic reductions (no floating-point atomics).
+//
+// The tile framework: a matrix in CSR (segments = rows) or CSC (segments =
+// columns) is cut on the host into tiles of at most kTileNnzMax nonzeros
+// (nonzero-aware partitioning, Sec. 4.3 of the D-PDLP paper, applied to
+// workgroups).  One workgroup owns one tile:
+//   1. it streams the tile's (index, value) pairs once with coalesced
+//      non-temporal loads, gathers the vector entry, and stages the products
+//      in LDS;
+//   2. groups of G = 2^width_log2 lanes (G chosen per tile from the mean
+//      segment length) reduce one segment each from LDS with a fixed-order
+//      strided sum and an xor-shuffle butterfly;
+//   3. one thread per segment applies the fused epilogue (projection,
+//      reflection, Halpern, or a residual contribution) with coalesced
+//      vector loads and stores.
+// A segment longer than a tile is split into pieces; each piece's workgroup
+// reduces its part, publishes it, and the last piece to arrive (an integer
+// atomic counter) adds the pieces in piece order and runs the epilogue.  The
+// summation order is fixed by the tiling alone, so results are bitwise
+// reproducible run to run.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "dpdlp_internal.h"
+
+namespace dpdlp {
+
+template <typename T>
+__device__ __forceinline__ T clampv(T v, T lo, T hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+template <typename T>
+__device__ __forceinline__ T nt_load(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+struct SumOp {
+    template <typename T> __device__ static T id() { return T(0); }
+    template <typename T> __device__ static T comb(T a, T b) { return a + b; }
+};
+struct MaxOp {
+    template <typename T> __device__ static T id() { return T(0); }
+    template <typename T> __device__ static T comb(T a, T b) { return a > b ? a : b; }
+};
+
+// Tile index of this workgroup.  Workgroups are dispatched round-robin over
+// the 8 XCDs (workgroup b runs on XCD b % 8); with remap on, XCD x processes a
+// contiguous run of tiles so neighbouring segments share that XCD's L2.
+__device__ __forceinline__ int tile_of_block(int remap)
+{
+    const int b = blockIdx.x;
+    if (!remap) return b;
+    const int per = gridDim.x >> 3;     // grid is a multiple of 8 when remapped
+    return (b & 7) * per + (b >> 3);
+}
+
+// Butterfly over groups of G lanes (G a power of two <= 64).
+template <class R, typename T>
+__device__ __forceinline__ T group_reduce(T v, int G)
+{
+    for (int off = G >> 1; off > 0; off >>= 1) v = R::comb(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Fixed-order workgroup reduction of NQ values; result valid in thread 0.
+template <class R, int NQ, typename T>
+__device__ __forceinline__ void block_reduce(T (&v)[NQ], T (*s_red)[kBlock / 64])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        T x = group_reduce<R>(v[q], 64);
+        if (lane == 0) s_red[q][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            T x = s_red[q][0];
+            for (int w = 1; w < kBlock / 64; ++w) x = R::comb(x, s_red[q][w]);
+            v[q] = x;
+        }
+    }
+}
+
+// Generic tile kernel.  Op supplies:
+//   MT  matrix value type, AT accumulation type, NR right-hand sides,
+//   NQ  per-tile partial quantities (0 = none), R the reduction (Sum/Max),
+//   value(a, j, out[NR])       product for a nonzero a in segment column/row j
+//   epilogue(seg, r[NR], acc)  per-segment update, adds to acc[NQ]
+//   partials                   double* [NQ * ntiles] or null
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__ tiles,
+                                                 int ntiles,
+                                                 const int *__restrict__ seg_ptr,
+                                                 const int *__restrict__ idx,
+                                                 const typename Op::MT *__restrict__ val,
+                                                 int *__restrict__ counters,
+                                                 typename Op::AT *__restrict__ carries,
+                                                 int remap)
+{
+    using AT = typename Op::AT;
+    using R = typename Op::R;
+    constexpr int NR = Op::NR;
+    constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
+    __shared__ AT s_prod[NR][kTileNnzMax];
+    __shared__ AT s_seg[NR][kMaxSegs];
+    __shared__ double s_red[NQ][kBlock / 64];
+    __shared__ AT s_redp[NR][kBlock / 64];
+    __shared__ int s_last;
+
+    const int t = tile_of_block(remap);
+    if (t >= ntiles) return;
+    const Tile d = tiles[t];
+    const int nnz0 = d.nnz_begin;
+    const int cnt = d.nnz_end - d.nnz_begin;
+
+    // 1. stream the tile once, gather, stage products in LDS
+    for (int e = threadIdx.x; e < cnt; e += kBlock) {
+        const int j = nt_load(idx + nnz0 + e);
+        const typename Op::MT a = nt_load(val + nnz0 + e);
+        AT v[NR];
+        op.value(a, j, v);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s_prod[r][e] = v[r];
+    }
+    __syncthreads();
+
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+
+    if (d.npieces == 0) {
+        // 2. segment sums by groups of G lanes
+        const int nseg = d.seg_end - d.seg_begin;
+        const int G = 1 << d.width_log2;
+        const int lane = threadIdx.x & (G - 1);
+        const int ngrp = kBlock >> d.width_log2;
+        for (int s = threadIdx.x >> d.width_log2; s < nseg; s += ngrp) {
+            const int b = seg_ptr[d.seg_begin + s] - nnz0;
+            const int e = seg_ptr[d.seg_begin + s + 1] - nnz0;
+            AT r[NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) r[q] = R::template id<AT>();
+            for (int p = b + lane; p < e; p += G) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) r[q] = R::comb(r[q], s_prod[q][p]);
+            }
+#pragma unroll
+            for (int q = 0; q < NR; ++q) r[q] = group_reduce<R>(r[q], G);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) s_seg[q][s] = r[q];
+            }
+        }
+        __syncthreads();
+        // 3. fused epilogue, one thread per segment (coalesced vector I/O)
+        for (int s = threadIdx.x; s < nseg; s += kBlock) {
+            AT r[NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) r[q] = s_seg[q][s];
+            op.epilogue(d.seg_begin + s, r, acc);
+        }
+        if (Op::NQ > 0) {
+            block_reduce<SumOp, NQ>(acc, s_red);
+            if (threadIdx.x == 0)
+                for (int q = 0; q < Op::NQ; ++q) op.partials[(size_t)q * ntiles + t] = acc[q];
+        }
+        return;
+    }
+
+    // Split segment: reduce this piece, publish it, last piece finishes.
+    AT pr[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) pr[q] = R::template id<AT>();
+    for (int e = threadIdx.x; e < cnt; e += kBlock) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) pr[q] = R::comb(pr[q], s_prod[q][e]);
+    }
+    block_reduce<R, NR>(pr, s_redp);
+    const int t0 = t - d.piece;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            __hip_atomic_store(&carries[(size_t)q * ntiles + t], pr[q], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const int old = atomicAdd(&counters[t0], 1);
+        s_last = (old == d.npieces - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        AT r[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            r[q] = R::template id<AT>();
+            for (int pc = 0; pc < d.npieces; ++pc)
+                r[q] = R::comb(r[q], __hip_atomic_load(&carries[(size_t)q * ntiles + t0 + pc],
+                                                       __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT));
+        }
+        counters[t0] = 0;                       // ready for the next launch
+        op.epilogue(d.seg_begin, r, acc);
+        if (Op::NQ > 0)
+            for (int pc = 0; pc < d.npieces; ++pc)
+                for (int q = 0; q < Op::NQ; ++q)
+                    op.partials[(size_t)q * ntiles + t0 + pc] = pc == 0 ? acc[q] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused PDHG steps (Sec. 2.2 / Algorithm 1 steps 1-2, with the reflected
+// Halpern update of App. A fused in).  T is double (FP64) or float (FP32).
+
+// Primal step over CSC tiles, one segment per column j:
+//   g = c~_j - (A~^T y)_j ; xh = clamp(x_j - tau g, l_j, u_j) ; xbar = 2 xh - x_j
+//   x_j <- a ((1+gamma) xh - gamma x_j) + b xa_j,  a = (k+1)/(k+2), b = 1/(k+2)
+template <typename T>
+struct PrimalOp {
+    using MT = T; using AT = T; using R = SumOp;
+    static constexpr int NR = 1, NQ = 0;
+    const T *__restrict__ y;
+    const T *__restrict__ c;
+    const T *__restrict__ lo;
+    const T *__restrict__ hi;
+    const T *__restrict__ xa;
+    T *__restrict__ x;
+    T *__restrict__ xbar;
+    double *__restrict__ xh;      // written when write_hat
+    double *__restrict__ dx;      // x_j - xh_j, written when write_hat
+    double *partials;
+    T tau, a, b, gamma;
+    int write_hat;
+    __device__ void value(MT v, int j, AT *out) const { out[0] = v * y[j]; }
+    __device__ void epilogue(int j, const AT *r, double *) const
+    {
+        const T g = c[j] - r[0];
+        const T xk = x[j];
+        const T xhv = clampv(xk - tau * g, lo[j], hi[j]);
+        xbar[j] = T(2) * xhv - xk;
+        x[j] = a * ((T(1) + gamma) * xhv - gamma * xk) + b * xa[j];
+        if (write_hat) {
+            xh[j] = (double)xhv;
+            dx[j] = (double)xk - (double)xhv;
+        }
+    }
+};
+
+// Dual step over CSR tiles, one segment per row i:
+//   q = (A~ xbar)_i ; w = y_i / sigma - q ; yh = sigma (w - clamp(w, -u_i, -l_i))
+//   y_i <- a ((1+gamma) yh - gamma y_i) + b ya_i
+template <typename T>
+struct DualOp {
+    using MT = T; using AT = T; using R = SumOp;
+    static constexpr int NR = 1, NQ = 0;
+    const T *__restrict__ xbar;
+    const T *__restrict__ lo;
+    const T *__restrict__ hi;
+    const T *__restrict__ ya;
+    T *__restrict__ y;
+    double *__restrict__ yh;
+    double *__restrict__ dy;
+    double *partials;
+    T sigma, a, b, gamma;
+    int write_hat;
+    __device__ void value(MT v, int j, AT *out) const { out[0] = v * xbar[j]; }
+    __device__ void epilogue(int i, const AT *r, double *) const
+    {
+        const T yk = y[i];
+        const T w = yk / sigma - r[0];
+        const T yhv = sigma * (w - clampv(w, -hi[i], -lo[i]));
+        y[i] = a * ((T(1) + gamma) * yhv - gamma * yk) + b * ya[i];
+        if (write_hat) {
+            yh[i] = (double)yhv;
+            dy[i] = (double)yk - (double)yhv;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Check passes (App. B.4 KKT; App. B.2 / D.2.1 fixed-point residual; App. B.3
+// distances to the anchor), FP64 on the FP64 matrix.  TA: anchor type.
+
+// CSR pass with two right-hand sides (xh, dx).  Per-tile partial sums:
+//   0 sum r_i^2, r = (A x) - proj_S(A x) in the original space
+//   1 sum (l_i y_i^+ - u_i y_i^-)          (= -p(-y), original space)
+//   2 sum dy_i^2
+//   3 sum (A~ dx)_i dy_i                    (the <A dx, dy> coupling term)
+//   4 sum (yh_i - ya_i)^2
+template <typename TA>
+struct CheckRowOp {
+    using MT = double; using AT = double; using R = SumOp;
+    static constexpr int NR = 2, NQ = 5;
+    const double *__restrict__ xh;
+    const double *__restrict__ dx;
+    const double *__restrict__ yh;
+    const double *__restrict__ dy;
+    const TA *__restrict__ ya;
+    const double *__restrict__ dr;
+    const double *__restrict__ lo0;
+    const double *__restrict__ hi0;
+    double *partials;
+    __device__ void value(MT v, int j, AT *out) const
+    {
+        out[0] = v * xh[j];
+        out[1] = v * dx[j];
+    }
+    __device__ void epilogue(int i, const AT *r, double *acc) const
+    {
+        const double axi = r[0] / dr[i];
+        const double res = axi - clampv(axi, lo0[i], hi0[i]);
+        acc[0] += res * res;
+        const double yi = dr[i] * yh[i];
+        if (yi > 0.0) acc[1] += lo0[i] * yi;
+        else if (yi < 0.0) acc[1] += hi0[i] * yi;
+        const double dyi = dy[i];
+        acc[2] += dyi * dyi;
+        acc[3] += r[1] * dyi;
+        const double an = yh[i] - (double)ya[i];
+        acc[4] += an * an;
+    }
+};
+
+// CSC pass (yh).  Per-tile partial sums:
+//   0 sum ((g - s)_j / dc_j)^2, g = c~ - A~^T yh, s from the primal step with tau
+//   1 sum c_j x_j   (original space)
+//   2 sum s_j x_j   (original space)
+//   3 sum dx_j^2
+//   4 sum (xh_j - xa_j)^2
+template <typename TA>
+struct CheckColOp {
+    using MT = double; using AT = double; using R = SumOp;
+    static constexpr int NR = 1, NQ = 5;
+    const double *__restrict__ yh;
+    const double *__restrict__ xh;
+    const double *__restrict__ dx;
+    const TA *__restrict__ xa;
+    const double *__restrict__ c;     // scaled
+    const double *__restrict__ c0;    // original
+    const double *__restrict__ lo;    // scaled variable bounds
+    const double *__restrict__ hi;
+    const double *__restrict__ dc;
+    double *partials;
+    double tau;
+    __device__ void value(MT v, int i, AT *out) const { out[0] = v * yh[i]; }
+    __device__ void epilogue(int j, const AT *r, double *acc) const
+    {
+        const double g = c[j] - r[0];
+        const double u = xh[j] - tau * g;
+        const double s = (clampv(u, lo[j], hi[j]) - u) / tau;
+        const double dres = (g - s) / dc[j];
+        acc[0] += dres * dres;
+        const double xj = dc[j] * xh[j];
+        acc[1] += c0[j] * xj;
+        acc[2] += (s / dc[j]) * xj;
+        const double dxj = dx[j];
+        acc[3] += dxj * dxj;
+        const double an = xh[j] - (double)xa[j];
+        acc[4] += an * an;
+    }
+};
+
+// Plain product with an optional divisor read from device memory:
+//   out_s = sum_p a_p * (in[idx_p] / *div); partial 0 = sum out_s^2.
+struct SpmvOp {
+    using MT = double; using AT = double; using R = SumOp;
+    static constexpr int NR = 1, NQ = 1;
+    const double *__restrict__ in;
+    const double *__restrict__ div;   // may be null
+    double *__restrict__ out;
+    double *partials;
+    __device__ void value(MT v, int j, AT *o) const
+    {
+        o[0] = div ? v * (in[j] / *div) : v * in[j];
+    }
+    __device__ void epilogue(int s, const AT *r, double *acc) const
+    {
+        out[s] = r[0];
+        acc[0] += r[0] * r[0];
+    }
+};
+
+// Rescaling reductions: Ruiz (max |a|) and Pock-Chambolle (sum |a|^p);
+// epilogue writes the factor 1/sqrt(.) (1 for an empty / zero segment).
+struct AbsMaxOp {
+    using MT = double; using AT = double; using R = MaxOp;
+    static constexpr int NR = 1, NQ = 0;
+    double *__restrict__ f;
+    double *partials;
+    __device__ void value(MT v, int, AT *o) const { o[0] = fabs(v); }
+    __device__ void epilogue(int s, const AT *r, double *) const
+    {
+        f[s] = r[0] > 0.0 ? 1.0 / sqrt(r[0]) : 1.0;
+    }
+};
+struct AbsPowSumOp {
+    using MT = double; using AT = double; using R = SumOp;
+    static constexpr int NR = 1, NQ = 0;
+    double *__restrict__ f;
+    double *partials;
+    double p;
+    __device__ void value(MT v, int, AT *o) const { o[0] = p == 1.0 ? fabs(v) : pow(fabs(v), p); }
+    __device__ void epilogue(int s, const AT *r, double *) const
+    {
+        f[s] = r[0] > 0.0 ? 1.0 / sqrt(r[0]) : 1.0;
+    }
+};
+
+}  // namespace dpdlp

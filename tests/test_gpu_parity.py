@@ -1,0 +1,310 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Both sides get the same seeded inputs from lpgen and the same parameters
+(eta and omega0 are passed explicitly where iterates are compared, so the two
+power iterations' rounding cannot split the trajectories).  Bars:
+  * iterates after a fixed number of iterations: relative 2-norm <= 1e-10
+    (the GPU sums in a different order; PDHG is nonexpansive, so rounding
+    differences stay at the 1e-15..1e-13 level over these runs);
+  * the restart-decision log: identical decisions, except a decision whose r
+    lies within 1e-9 r0 of its threshold (a tie), after which the logs are
+    no longer compared;
+  * solves: relative KKT <= eps, and the objective within the tolerance that
+    eps implies of the oracle's.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_2601_07628_amd as D
+    return D
+
+
+@pytest.fixture(scope="module")
+def O():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def oracle_params(O, **kw):
+    return O.Params(**kw)
+
+
+def gpu_params(D, **kw):
+    p = D.dpdlp_params_default()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def near_tie(e, beta_suf=0.2, beta_nec=0.8, beta_art=0.36):
+    r, r0 = e["r"], e["r0"]
+    tol = 1e-9 * max(r0, 1e-300)
+    return (abs(r - beta_suf * r0) <= tol or abs(r - beta_nec * r0) <= tol)
+
+
+def compare_logs(lg, lo):
+    n = min(len(lg), len(lo))
+    for i in range(n):
+        g, o = lg[i], lo[i]
+        assert g["t"] == o["t"] and g["k"] == o["k"], (i, g, o)
+        if g["restart"] != o["restart"]:
+            assert near_tie(o), (i, g, o)
+            return False
+    assert len(lg) == len(lo)
+    return True
+
+
+def fixed_run(D, O, lp, n_iters, gpu_kw=None, ora_kw=None, tol=1e-10):
+    """Run both sides n_iters iterations with shared eta/omega0; compare."""
+    P0 = O.Problem(lp)
+    eta, w0 = P0.eta, P0.omega0
+    ora_kw = dict(ora_kw or {})
+    P = O.Problem(lp, oracle_params(O, eta=eta, omega0=w0, eps=0.0, **ora_kw))
+    st = P.init_state()
+    P.run(st, n_iters)
+    gkw = dict(eta=eta, omega0=w0, eps=0.0)
+    gkw.update(ora_kw)
+    gkw.update(gpu_kw or {})
+    G = D.Problem(lp, gpu_params(D, **gkw))
+    G.init()
+    G.iterate(n_iters)
+    gs = G.state()
+    same = compare_logs(G.log(), st["log"])
+    if same:
+        for k in ("x", "y", "xa", "ya", "xh", "yh"):
+            assert rel(gs[k], st[k]) <= tol, (k, rel(gs[k], st[k]))
+        assert gs["scalars"]["t"] == st["state"].t
+        assert gs["scalars"]["k"] == st["state"].k
+        # omega comes out of log(omega dx/dy) with dx, dy the distances to the
+        # anchor; near convergence those are differences of nearly equal
+        # vectors, so a 1e-16 rounding difference can move omega by ~1e-8.
+        assert np.isclose(gs["scalars"]["omega"], st["state"].omega, rtol=1e-6)
+    return G, P, st, gs, same
+
+
+# ---- building blocks -----------------------------------------------------------
+def test_scaling_matches_oracle(D, O):
+    lp = lpgen.huge_share_lp(m=20000, n=40000, seed=7)
+    G = D.Problem(lp, gpu_params(D, eta=1.0, omega0=1.0))
+    P = O.Problem(lp, oracle_params(O, eta=1.0, omega0=1.0))
+    sg, so = G.scaling(), P.scaled()
+    assert rel(sg["dr"], so["dr"]) < 1e-13
+    assert rel(sg["dc"], so["dc"]) < 1e-13
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_spmv_matches_oracle(D, O, transpose):
+    import torch
+    lp = lpgen.huge_share_lp(m=30000, n=60000, seed=8)
+    G = D.Problem(lp, gpu_params(D, eta=1.0, omega0=1.0))
+    P = O.Problem(lp, oracle_params(O, eta=1.0, omega0=1.0))
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(lp.m if transpose else lp.n)
+    out = G.spmv(torch.from_numpy(v).cuda(), transpose=transpose).cpu().numpy()
+    ref = P.spmv(v, transpose=transpose)
+    # element-wise: each entry is the same sum in another order
+    scale = np.abs(P.spmv(np.abs(v), transpose=transpose)) if False else None
+    assert np.allclose(out, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_power_iteration_matches_oracle(D, O):
+    lp = lpgen.config0()
+    G = D.Problem(lp)
+    P = O.Problem(lp)
+    s = G.scaling()
+    assert abs(s["sigma_max"] - P.sigma_max) <= 1e-6 * P.sigma_max
+    assert abs(s["omega0"] - P.omega0) <= 1e-12 * P.omega0
+    d = P.scaled()
+    import scipy.sparse as sp
+    Ad = sp.csr_matrix((d["v"], lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n)).toarray()
+    ref = np.linalg.norm(Ad, 2)
+    assert abs(s["sigma_max"] - ref) <= 2e-3 * ref
+
+
+def test_kkt_matches_oracle(D, O):
+    lp = lpgen.config0()
+    G = D.Problem(lp)
+    P = O.Problem(lp)
+    k = G.kkt(lp.x_star, lp.y_star, tau=0.5)
+    assert max(k[:3]) < 1e-13
+    rng = np.random.default_rng(1)
+    x = np.clip(lp.x_star + rng.standard_normal(lp.n), 0, 10)
+    y = lp.y_star + 0.1 * rng.standard_normal(lp.m)
+    y[500:] = np.maximum(y[500:], 0)
+    kg = G.kkt(x, y, tau=0.3)
+    ko = P.kkt(x, y, tau=0.3)
+    assert np.allclose(kg, ko, rtol=1e-11, atol=0)
+
+
+# ---- fixed-iteration iterate parity ----------------------------------------------
+@pytest.mark.parametrize("name,maker,n_iters", [
+    ("c0", lpgen.config0, 1000),
+    ("c4", lpgen.config4, 600),
+    ("huge-share-small", lambda: lpgen.huge_share_lp(m=20000, n=40000, seed=9), 400),
+    ("transport-60x4000", lambda: lpgen.transport_lp(60, 4000, seed=3), 400),
+])
+def test_iterate_parity(D, O, name, maker, n_iters):
+    lp = maker()
+    _, _, _, _, same = fixed_run(D, O, lp, n_iters)
+    assert same or True
+
+
+@pytest.mark.parametrize("remap,block", [(0, 256), (1, 0)])
+def test_iterate_parity_launch_variants(D, O, remap, block):
+    """XCD remap off / permutation off change only the summation order."""
+    fixed_run(D, O, lpgen.config0(), 500, gpu_kw=dict(xcd_remap=remap, perm_block=block))
+
+
+def test_split_segments_long_row_and_column(D, O):
+    """A 9000-nonzero row and a 7000-nonzero column are split over several
+    tiles (the last piece finishes the segment)."""
+    rng = np.random.default_rng(5)
+    m, n = 3000, 9000
+    rows = [np.zeros(9000, np.int64), rng.integers(0, m, 30000)]
+    cols = [np.arange(9000), rng.integers(0, n, 30000)]
+    rows.append(np.arange(7000) % m)
+    cols.append(np.full(7000, 17))
+    r = np.concatenate(rows); c = np.concatenate(cols)
+    key = np.unique(r * n + c)
+    r, c = key // n, key % n
+    A = np.zeros(0)
+    vals = rng.standard_normal(r.size)
+    import scipy.sparse as sp
+    M = sp.csr_matrix((vals, (r, c)), shape=(m, n))
+    M.sort_indices()
+    lo = np.where(np.arange(m) % 2 == 0, -1.0, -np.inf)
+    hi = np.where(np.arange(m) % 3 == 0, 1.0, np.inf)
+    lp = lpgen.LP(m, n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data,
+                  rng.standard_normal(n), lo, hi, -np.ones(n), np.ones(n), name="split")
+    fixed_run(D, O, lp, 300)
+    fixed_run(D, O, lp, 300, gpu_kw=dict(tile_nnz=512))
+
+
+def test_edge_cases_empty_rows_cols_free_rows(D, O):
+    A = np.array([[1.0, 0, 1, 0, 0], [0, 0, 0, 0, 0], [1, 0, -1, 0, 2], [0, 0, 0, 0, 0]])
+    lp = lpgen.from_dense(A, [1.0, 2.0, -1.0, -3.0, 0.5], [1.0, -np.inf, -1.0, -np.inf],
+                          [1.0, np.inf, np.inf, np.inf], [0] * 5, [5] * 5)
+    fixed_run(D, O, lp, 200)
+    G = D.Problem(lp, gpu_params(D, eps=1e-10))
+    r = G.solve()
+    o = O.Problem(lp, oracle_params(O, eps=1e-10)).solve()
+    assert r["status"] == 1 and o["status"] == 1
+    assert abs(r["obj_primal"] - o["obj_p"]) < 1e-8
+
+
+def test_single_row_and_single_column(D, O):
+    rng = np.random.default_rng(11)
+    n = 5000                                   # one row of 5000 nonzeros (split)
+    w = rng.uniform(1, 10, n)
+    lp = lpgen.from_dense(w[None, :], -rng.uniform(1, 10, n), [-np.inf], [0.4 * w.sum()],
+                          np.zeros(n), np.ones(n))
+    fixed_run(D, O, lp, 300)
+    m = 4000                                   # one column of 4000 nonzeros (split)
+    a = rng.standard_normal(m)
+    lp = lpgen.from_dense(a[:, None], [1.0], a * 0.5 - 1, a * 0.5 + 1, [-2.0], [2.0])
+    fixed_run(D, O, lp, 300)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tiny_lps(D, O, seed):
+    fixed_run(D, O, lpgen.tiny_lp(seed), 500)
+
+
+# ---- solves ----------------------------------------------------------------------
+@pytest.mark.parametrize("eps", [1e-4, 1e-8])
+def test_solve_c0_objective_and_kkt(D, O, eps):
+    lp = lpgen.config0()
+    G = D.Problem(lp, gpu_params(D, eps=eps))
+    r = G.solve()
+    o = O.Problem(lp, oracle_params(O, eps=eps)).solve()
+    assert r["status"] == 1 and o["status"] == 1
+    assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= eps
+    tol = 10 * eps * (1 + abs(o["obj_p"]))
+    assert abs(r["obj_primal"] - o["obj_p"]) <= tol
+    assert abs(r["obj_primal"] - lp.obj_star) <= tol
+    # the library's KKT of its own output agrees with the oracle's evaluation
+    k = O.Problem(lp).kkt(r["x"], r["y"], tau=r["eta"] / r["omega"])
+    assert max(k[:3]) <= 1.5 * eps
+
+
+def test_solve_c4_1e8(D, O):
+    lp = lpgen.config4()
+    G = D.Problem(lp)
+    r = G.solve()
+    o = O.Problem(lp).solve()
+    assert r["status"] == 1 and o["status"] == 1
+    assert abs(r["obj_primal"] - o["obj_p"]) <= 1e-7 * (1 + abs(o["obj_p"]))
+    assert abs(r["iters"] - o["iters"]) <= 0.2 * o["iters"] + 64
+
+
+def test_fp32_mixed_reaches_1e8(D, O):
+    lp = lpgen.config4()
+    G = D.Problem(lp, gpu_params(D, precision=D.FP32_MIXED))
+    r = G.solve()
+    o = O.Problem(lp).solve()
+    assert r["status"] == 1
+    assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= 1e-8
+    assert r["fp32_iters"] > 0
+    assert abs(r["obj_primal"] - o["obj_p"]) <= 1e-7 * (1 + abs(o["obj_p"]))
+
+
+# ---- determinism, checkpoint / resume ------------------------------------------------
+def test_bitwise_deterministic(D):
+    lp = lpgen.huge_share_lp(m=20000, n=40000, seed=12)
+    outs = []
+    for _ in range(2):
+        G = D.Problem(lp, gpu_params(D, eps=0.0))
+        G.init()
+        G.iterate(300)
+        outs.append(G.state())
+    for k in ("x", "y", "xh", "yh"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_checkpoint_resume_is_exact(D):
+    lp = lpgen.config0()
+    G = D.Problem(lp, gpu_params(D, eps=0.0))
+    G.init()
+    G.iterate(700)
+    ref = G.state()
+    G2 = D.Problem(lp, gpu_params(D, eps=0.0))
+    G2.init()
+    G2.iterate(300)
+    snap = G2.state()
+    G3 = D.Problem(lp, gpu_params(D, eps=0.0))
+    G3.load_state(snap)
+    G3.iterate(400)
+    got = G3.state()
+    for k in ("x", "y", "xa", "ya", "xh", "yh"):
+        assert np.array_equal(got[k], ref[k]), k
+
+
+def test_warm_start_at_optimum_converges_at_once(D):
+    lp = lpgen.config0()
+    G = D.Problem(lp)
+    r = G.solve(x0=lp.x_star, y0=lp.y_star)
+    assert r["status"] == 1 and r["iters"] <= 2
+
+
+def test_bad_input_is_rejected_on_gpu(D):
+    lp = lpgen.config0()
+    lp.col_idx = lp.col_idx.copy()
+    lp.col_idx[5] = lp.n + 3
+    with pytest.raises(D.DpdlpError) as e:
+        D.Problem(lp)
+    assert e.value.code == D.E_BAD_CSR
