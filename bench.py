@@ -1,0 +1,265 @@
+#!/usr/bin/env python
+"""Benchmark of the single-GPU restarted Halpern PDHG hot path.
+
+One step = one block of K = 64 PDHG iterations of the solver loop on the
+config-1 LP (one GPU's share of a huge LP: m = 2M, n = 4M, ~40M nonzeros,
+FP64): 64 fused primal + fused dual iterations, the KKT / fixed-point-residual
+check passes, the control kernel (restart + PID), and any restart, exactly as
+dpdlp_iterate runs them.  Setup (permutation, CSC, tiles, rescaling, power
+iteration) happens once before the timed region and is reported separately.
+
+Prints ONE JSON line: iterations/s (value), the roofline of the dominant
+kernel (algorithmic bytes / HIP-event launch duration, against 8 TB/s), the
+oracle's CPU iterations/s on a bounded sample, and extra fields: SpMV GB/s,
+FP32-mixed iterations/s on the same instance, time-to-tolerance on the
+smaller instances.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-1e-8 KKT & PDHG iters/s: FP64 vs FP32-mixed vs warm-start; SpMV GB/s"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2601_07628_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    e = d.get("kernels", {}).get(f"{workload}/{kernel}")
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def gpu_params(D, **kw):
+    p = D.dpdlp_params_default()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def timed_steps(G, steps, iters_per_step, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        G.iterate(iters_per_step)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(lp, n_iters):
+    """The FP64 oracle on the same instance, timed on this host."""
+    import oracle
+    t0 = time.perf_counter()
+    P0 = oracle.Problem(lp, oracle.Params(eta=1.0, omega0=1.0, eps=0.0))
+    sig, _ = P0.sigma_max_power(max_iters=10, tol=0.0)
+    prep0 = time.perf_counter() - t0
+    del P0
+    t0 = time.perf_counter()
+    P = oracle.Problem(lp, oracle.Params(eta=0.9 / sig, omega0=0.0, eps=0.0))
+    prep = time.perf_counter() - t0
+    st = P.init_state()
+    t0 = time.perf_counter()
+    P.run(st, n_iters)
+    el = time.perf_counter() - t0
+    return dict(value=n_iters / el, unit="PDHG iters/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=(f"{n_iters} FP64 PDHG iterations (checks every 64, as on the GPU) "
+                        f"of the oracle on the same config-1 instance after its setup "
+                        f"(CSC + 10 Ruiz + Pock-Chambolle, {prep:.1f} s; step size from a "
+                        f"10-step power estimate, {prep0:.1f} s), OpenMP threads = "
+                        f"{oracle.num_threads()}"),
+                seconds=el)
+
+
+def time_to_tol(D, lp, torch, **kw):
+    out = {}
+    for eps in (1e-4, 1e-8):
+        G = D.Problem(lp, gpu_params(D, eps=eps, **kw), stream=torch.cuda.current_stream())
+        G.solve()                              # warm-up (kernels, allocator)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = G.solve()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"{eps:g}"] = dict(seconds=round(el, 5), iters=int(r["iters"]),
+                               status=D.dpdlp_status_string(r["status"]),
+                               kkt=max(r["r_primal"], r["r_dual"], r["r_gap"]),
+                               obj=r["obj_primal"], fp32_iters=int(r["fp32_iters"]),
+                               setup_s=round(r["setup_seconds"], 4))
+        G.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--iters-per-step", type=int, default=64)
+    ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy a 256 MiB buffer (device to device), a kernel of "
+                         "known size that calibrates the HBM byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import lpgen
+    import paper_2601_07628_amd as D
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    if args.calib_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
+    log("generating config 1 (m=2M, n=4M, ~40M nonzeros)")
+    t0 = time.perf_counter()
+    lp = lpgen.config1()
+    log(f"config 1 ready in {time.perf_counter() - t0:.1f} s: {lp.describe()}")
+
+    G = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9), stream=stream)
+    s = G.scaling()
+    G.init()
+    setup_s = G.result(want_xy=False)["setup_seconds"]
+    log(f"setup {setup_s:.2f} s (sigma_max {s['sigma_max']:.6g})")
+    ips = args.iters_per_step
+    for _ in range(args.warmup):
+        G.iterate(ips)
+    torch.cuda.synchronize()
+    G.profile_enable(True)
+    el = timed_steps(G, args.steps, ips, torch)
+    prof = G.profile()
+    G.profile_enable(False)
+    res = G.result(want_xy=False)
+    iters = args.steps * ips
+    value = iters / el
+    log(f"FP64: {value:.1f} iters/s ({1e3 * el / args.steps:.3f} ms per {ips}-iteration step)")
+
+    # dominant kernel of the step: the one with the largest total event time
+    fused = {k: prof[k] for k in ("primal", "dual") if prof[k]["launches"]}
+    dom = max(fused, key=lambda k: fused[k]["total_ms"])
+    avg_ms = fused[dom]["total_ms"] / fused[dom]["launches"]
+    achieved = fused[dom]["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(dom, "c1")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "kernel": f"fused_{dom}_step_fp64",
+            "avg_launch_ms": round(avg_ms, 5),
+            "alg_bytes_per_launch": fused[dom]["bytes_per_launch"]}
+    kern = {k: dict(avg_ms=round(v["total_ms"] / v["launches"], 5), launches=v["launches"],
+                    alg_GBps=round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"]) / 1e6, 1)
+                    if v["bytes_per_launch"] else None)
+            for k, v in prof.items() if v["launches"]}
+    step_bytes = prof["primal"]["bytes_per_launch"] + prof["dual"]["bytes_per_launch"]
+
+    extra = {}
+    if not args.no_extra:
+        ms_r, b_r = G.time_kernel(2, 20)
+        ms_c, b_c = G.time_kernel(3, 20)
+        extra["spmv_GBps"] = {"csr_Ax": round(b_r / ms_r / 1e6, 1),
+                              "csc_ATy": round(b_c / ms_c / 1e6, 1),
+                              "csr_ms": round(ms_r, 4), "csc_ms": round(ms_c, 4)}
+        log(f"SpMV: {extra['spmv_GBps']}")
+    G.close()
+    del G
+
+    if not args.no_extra:
+        G32 = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9,
+                                        precision=D.FP32_MIXED, fp32_stall_checks=10**6,
+                                        fp32_switch_tol=0.0), stream=stream)
+        G32.init()
+        G32.iterate(ips)
+        steps32 = max(5, args.steps // 2)
+        el32 = timed_steps(G32, steps32, ips, torch)
+        r32 = G32.result(want_xy=False)
+        extra["fp32_mixed_c1"] = {"iters_per_s": round(steps32 * ips / el32, 1),
+                                  "in_fp32": int(r32["fp32_iters"]) == int(r32["iters"])}
+        log(f"FP32-mixed: {extra['fp32_mixed_c1']}")
+        G32.close()
+        del G32
+        for name, mk in (("c0", lpgen.config0), ("c4", lpgen.config4)):
+            inst = mk()
+            extra[f"time_to_tol_{name}"] = {
+                "fp64": time_to_tol(D, inst, torch),
+                "fp32_mixed": time_to_tol(D, inst, torch, precision=D.FP32_MIXED)}
+            log(f"time-to-tolerance {name}: {extra[f'time_to_tol_{name}']}")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"CPU baseline: oracle, {args.cpu_iters} iterations on config 1")
+        cpu = cpu_baseline(lp, args.cpu_iters)
+        log(f"CPU baseline: {cpu['value']:.3f} iters/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "PDHG iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator; the paper's data sets are not available)",
+        "config": {"workload": "c1: one GPU's share of a huge LP, m=2,000,000, n=4,000,000, "
+                               f"nnz={lp.nnz}, Zipf column degrees, 10% heavy rows, FP64",
+                   "iters_per_step": ips, "check_period": 64, "m": lp.m, "n": lp.n,
+                   "nnz": lp.nnz},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "step_alg_bytes_per_iter": step_bytes,
+        "step_alg_GBps": round(step_bytes * value / 1e9, 1),
+        "kernels": kern,
+        "setup_seconds": round(setup_s, 3),
+        "restarts_in_run": int(res["restarts"]),
+        "kernel_source": kernel_source_hash(),
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

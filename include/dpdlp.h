@@ -141,6 +141,22 @@ int dpdlp_problem_create(const dpdlp_csr_lp *lp, const dpdlp_params *params,
                          void *stream, dpdlp_problem **out);
 int dpdlp_problem_destroy(dpdlp_problem *prob);
 
+/* Replace the objective and bounds of a prepared problem by those of another
+ * member of the same family (same A): c [n], con_lo/con_hi [m], var_lo/var_hi
+ * [n]; any may be NULL to keep the current values.  The matrix scaling,
+ * tiles and step size are kept; the scaled vectors, the norms and omega0 are
+ * recomputed.  The next dpdlp_iterate starts from a fresh dpdlp_init.
+ * Errors: BAD_BOUNDS (as dpdlp_validate), HIP.                            */
+int dpdlp_problem_update_data(dpdlp_problem *prob, const double *c, const double *con_lo,
+                              const double *con_hi, const double *var_lo,
+                              const double *var_hi, int32_t mem_kind, void *stream);
+
+/* Change the run-time parameters of a prepared problem: eps, max_iters,
+ * time_limit, check_period, gamma, beta_*, kp/ki/kd, xcd_remap and the FP32
+ * switch rule.  The other fields (scaling, step size, permutation, tiles,
+ * precision) are fixed at creation and ignored here.  Errors: INVALID_ARG. */
+int dpdlp_set_params(dpdlp_problem *prob, const dpdlp_params *params);
+
 /* Start from (x0, y0) (original space; NULL = zeros): the point is scaled,
  * clamped into X and projected onto Y, and becomes the epoch anchor.  The
  * pointers are host or device per mem_kind.                              */
@@ -191,7 +207,9 @@ int dpdlp_spmv(dpdlp_problem *prob, int32_t transpose, const double *in, double 
 
 /* KKT of the original problem at an original-space point (x, y) with primal
  * step tau (tau <= 0: the current eta/omega) (App. B.4).  out5 (host):
- * r_primal, r_dual, r_gap, obj_primal, obj_dual.  x, y per mem_kind.       */
+ * r_primal, r_dual, r_gap, obj_primal, obj_dual.  x, y per mem_kind; with
+ * x = y = NULL the point is the current start point of dpdlp_init (after
+ * its clamping into X and projection onto Y).                             */
 int dpdlp_kkt(dpdlp_problem *prob, const double *x, const double *y, double tau,
               int32_t mem_kind, double *out5, void *stream);
 
@@ -219,6 +237,63 @@ int dpdlp_time_kernel(dpdlp_problem *prob, int32_t which, int32_t reps, void *st
 int dpdlp_profile_enable(dpdlp_problem *prob, int32_t enable);
 int dpdlp_get_profile(dpdlp_problem *prob, double *total_ms, int64_t *launches,
                       double *bytes_per_launch);
+
+/* ---- learned warm start --------------------------------------------------
+ * Not in the paper (which starts from a given (x0, y0), Algorithm 1 input):
+ * a bipartite message-passing network on the row/column graph of the scaled
+ * matrix A~ of a prepared problem predicts a start point for problems of the
+ * same family (same A and variable bounds; other c and row bounds).
+ *   inputs  column j: [c~_j, c~_j - c~ref_j, x~ref_j, has_lo, has_hi,
+ *                      lo~_j or 0, hi~_j or 0, 1, 0 x 8]   (x~ = x / D_c)
+ *           row i:    [b~_i, b~_i - b~ref_i, y~ref_i, is_eq, has_lo, has_hi,
+ *                      0, 1, 0 x 8]  (y~ = y / D_r; b = finite lower bound,
+ *                      else finite upper bound, else 0; c~ = D_c c, b~ = D_r b)
+ *   network H_c0 = relu(X_c W_cin), H_r0 = relu(X_r W_rin); per layer
+ *           H_r = relu([H_r, A~ H_c] W_r), H_c = relu([H_c, A~^T H_r] W_c)
+ *           (BF16 activations and weights, FP32 accumulation on the MFMA
+ *           units); x~0 = x~ref + H_c w_x, y~0 = y~ref + H_r w_y.
+ *   params  one FP32 vector: W_cin [16x128], W_rin [16x128], then per layer
+ *           W_c [256x128], W_r [256x128] (row-major, input feature major),
+ *           then w_x [128], w_y [128].
+ *   loss    mean((x~0 - x~*)^2) + mean((y~0 - y~*)^2).
+ * Vectors are in the original order and space; pointers per mem_kind.     */
+typedef struct dpdlp_gnn dpdlp_gnn;
+
+/* Network with `layers` message-passing layers on prob's graph (prob must
+ * outlive it).  Parameters start at zero: set them with dpdlp_gnn_set_params. */
+int dpdlp_gnn_create(dpdlp_problem *prob, int32_t layers, void *stream, dpdlp_gnn **out);
+int dpdlp_gnn_destroy(dpdlp_gnn *gnn);
+int64_t dpdlp_gnn_num_params(dpdlp_gnn *gnn);
+/* Host FP32 parameter vector (count = dpdlp_gnn_num_params); resets Adam.  */
+int dpdlp_gnn_set_params(dpdlp_gnn *gnn, const float *params, int64_t count, void *stream);
+/* Copy the FP32 parameters and the last gradient to host (either may be NULL). */
+int dpdlp_gnn_get_params(dpdlp_gnn *gnn, float *params, float *grads, int64_t count,
+                         void *stream);
+/* Family reference: c_ref [n], b_ref [m] (per-row b as above), and the
+ * reference solution x_ref [n], y_ref [m] (original space).               */
+int dpdlp_gnn_set_reference(dpdlp_gnn *gnn, const double *c_ref, const double *b_ref,
+                            const double *x_ref, const double *y_ref, int32_t mem_kind,
+                            void *stream);
+/* The instance whose start point is predicted: c [n], con_lo/con_hi [m].   */
+int dpdlp_gnn_set_instance(dpdlp_gnn *gnn, const double *c, const double *con_lo,
+                           const double *con_hi, int32_t mem_kind, void *stream);
+/* Predicted start point in the original space (x0 [n], y0 [m]; may be NULL). */
+int dpdlp_gnn_forward(dpdlp_gnn *gnn, double *x0, double *y0, int32_t mem_kind, void *stream);
+/* Forward + backward against a target solution (original space); the
+ * gradient stays on the device for dpdlp_gnn_adam_step; loss2 (host, may be
+ * NULL) receives the two mean squared errors (columns, rows).              */
+int dpdlp_gnn_backward(dpdlp_gnn *gnn, const double *x_target, const double *y_target,
+                       int32_t mem_kind, double *loss2, void *stream);
+/* One Adam step on the FP32 master weights (bias-corrected), refreshing the
+ * BF16 copies used by the forward pass.                                   */
+int dpdlp_gnn_adam_step(dpdlp_gnn *gnn, double lr, double beta1, double beta2, double eps,
+                        void *stream);
+/* The network's MFMA GEMM kernel alone (tests): C [M x Nc] FP32 (row stride
+ * ldc) = A [M x K] B [K x Nc] with BF16 bit patterns, A(i,k) at
+ * A[i*a_rs + k*a_cs], B(k,j) at B[k*b_rs + j*b_cs].  Device pointers.    */
+int dpdlp_gnn_gemm_test(const uint16_t *A, long a_rs, long a_cs, const uint16_t *B, long b_rs,
+                        long b_cs, float *C, long ldc, int32_t M, int32_t Nc, int32_t K,
+                        void *stream);
 
 /* ---- host-only preprocessing, callable without a GPU -------------------- */
 

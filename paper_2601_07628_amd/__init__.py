@@ -95,12 +95,16 @@ class LogRec(C.Structure):
 # Every symbol include/dpdlp.h declares (checked by the CPU test suite).
 EXPORTS = (
     "dpdlp_params_default", "dpdlp_problem_create", "dpdlp_problem_destroy",
+    "dpdlp_problem_update_data", "dpdlp_set_params",
     "dpdlp_init", "dpdlp_iterate", "dpdlp_solve", "dpdlp_get_result",
     "dpdlp_state_export", "dpdlp_state_import", "dpdlp_get_log", "dpdlp_spmv",
     "dpdlp_kkt", "dpdlp_get_scaling", "dpdlp_time_kernel",
     "dpdlp_profile_enable", "dpdlp_get_profile", "dpdlp_validate",
     "dpdlp_block_permutation", "dpdlp_build_tiles", "dpdlp_status_string",
-    "dpdlp_last_error",
+    "dpdlp_last_error", "dpdlp_gnn_create", "dpdlp_gnn_destroy", "dpdlp_gnn_num_params",
+    "dpdlp_gnn_set_params", "dpdlp_gnn_get_params", "dpdlp_gnn_set_reference",
+    "dpdlp_gnn_set_instance", "dpdlp_gnn_forward", "dpdlp_gnn_backward",
+    "dpdlp_gnn_adam_step", "dpdlp_gnn_gemm_test",
 )
 
 
@@ -115,7 +119,9 @@ def _load():
         "dpdlp_params_default": ([C.POINTER(Params)], None),
         "dpdlp_problem_create": ([C.POINTER(CsrLP), C.POINTER(Params), vp, C.POINTER(vp)], C.c_int),
         "dpdlp_problem_destroy": ([vp], C.c_int),
+        "dpdlp_problem_update_data": ([vp, vp, vp, vp, vp, vp, i32, vp], C.c_int),
         "dpdlp_init": ([vp, vp, vp, i32, vp], C.c_int),
+        "dpdlp_set_params": ([vp, C.POINTER(Params)], C.c_int),
         "dpdlp_iterate": ([vp, i64, vp], C.c_int),
         "dpdlp_solve": ([vp, vp, vp, vp, vp, i32, C.POINTER(Result), vp], C.c_int),
         "dpdlp_get_result": ([vp, vp, vp, i32, C.POINTER(Result), vp], C.c_int),
@@ -132,6 +138,18 @@ def _load():
         "dpdlp_block_permutation": ([i32, i32, u64, vp], C.c_int),
         "dpdlp_build_tiles": ([vp, i32, i32, vp, C.POINTER(i32)], C.c_int),
         "dpdlp_status_string": ([i32], C.c_char_p),
+        "dpdlp_gnn_create": ([vp, i32, vp, C.POINTER(vp)], C.c_int),
+        "dpdlp_gnn_destroy": ([vp], C.c_int),
+        "dpdlp_gnn_num_params": ([vp], i64),
+        "dpdlp_gnn_set_params": ([vp, vp, i64, vp], C.c_int),
+        "dpdlp_gnn_get_params": ([vp, vp, vp, i64, vp], C.c_int),
+        "dpdlp_gnn_set_reference": ([vp, vp, vp, vp, vp, i32, vp], C.c_int),
+        "dpdlp_gnn_set_instance": ([vp, vp, vp, vp, i32, vp], C.c_int),
+        "dpdlp_gnn_forward": ([vp, vp, vp, i32, vp], C.c_int),
+        "dpdlp_gnn_backward": ([vp, vp, vp, i32, vp, vp], C.c_int),
+        "dpdlp_gnn_adam_step": ([vp, dbl, dbl, dbl, dbl, vp], C.c_int),
+        "dpdlp_gnn_gemm_test": ([vp, C.c_long, C.c_long, vp, C.c_long, C.c_long, vp, C.c_long,
+                                 i32, i32, i32, vp], C.c_int),
         "dpdlp_last_error": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -280,6 +298,20 @@ class Problem:
     def _s(self):
         return _stream(self.stream)
 
+    def set_params(self, **kw):
+        """Change run-time parameters (eps, max_iters, time_limit, ...)."""
+        for k, v in kw.items():
+            if not hasattr(self.params, k):
+                raise AttributeError(f"no parameter {k}")
+            setattr(self.params, k, v)
+        _check(_lib.dpdlp_set_params(self.h, C.byref(self.params)))
+
+    def update_data(self, c=None, con_lo=None, con_hi=None, var_lo=None, var_hi=None):
+        """Another member of the same family: new objective / bounds, same A."""
+        a = [None if v is None else np.ascontiguousarray(v, np.float64)
+             for v in (c, con_lo, con_hi, var_lo, var_hi)]
+        _check(_lib.dpdlp_problem_update_data(self.h, *[_ptr(v) for v in a], MEM_HOST, self._s))
+
     def init(self, x0=None, y0=None):
         x0 = None if x0 is None else np.ascontiguousarray(x0, np.float64)
         y0 = None if y0 is None else np.ascontiguousarray(y0, np.float64)
@@ -341,11 +373,13 @@ class Problem:
         _check(_lib.dpdlp_spmv(self.h, int(transpose), _ptr(vec), _ptr(out), self._s))
         return out
 
-    def kkt(self, x, y, tau: float = 0.0):
+    def kkt(self, x=None, y=None, tau: float = 0.0):
+        """KKT triple + objectives at (x, y), or at the current start point."""
         out = np.zeros(5)
-        _check(_lib.dpdlp_kkt(self.h, _ptr(np.ascontiguousarray(x, np.float64)),
-                              _ptr(np.ascontiguousarray(y, np.float64)), float(tau),
-                              MEM_HOST, _ptr(out), self._s))
+        xp = None if x is None else np.ascontiguousarray(x, np.float64)
+        yp = None if y is None else np.ascontiguousarray(y, np.float64)
+        _check(_lib.dpdlp_kkt(self.h, _ptr(xp), _ptr(yp), float(tau), MEM_HOST, _ptr(out),
+                              self._s))
         return out
 
     def scaling(self):
@@ -371,3 +405,83 @@ class Problem:
         return {name: dict(total_ms=float(ms[i]), launches=int(n[i]),
                            bytes_per_launch=float(b[i]))
                 for i, name in enumerate(KERNEL_CLASSES)}
+
+
+# ---- learned warm start -------------------------------------------------------
+def row_b(con_lo, con_hi):
+    """Per-row right-hand side used by the network's row features: the finite
+    lower bound, else the finite upper bound, else 0."""
+    lo = np.asarray(con_lo, np.float64)
+    hi = np.asarray(con_hi, np.float64)
+    return np.where(np.isfinite(lo), lo, np.where(np.isfinite(hi), hi, 0.0))
+
+
+class WarmStartNet:
+    """The warm-start network on a prepared problem's graph (C ABI wrapper)."""
+
+    def __init__(self, problem: Problem, layers: int = 3, stream=None):
+        self.problem = problem
+        self.stream = stream
+        h = C.c_void_p()
+        _check(_lib.dpdlp_gnn_create(problem.h, layers, _stream(stream), C.byref(h)))
+        self.h = h
+        self.layers = layers
+        self.n_params = int(_lib.dpdlp_gnn_num_params(h))
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            _lib.dpdlp_gnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _s(self):
+        return _stream(self.stream)
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        _check(_lib.dpdlp_gnn_set_params(self.h, _ptr(p), p.size, self._s))
+
+    def params(self, grads=False):
+        p = np.zeros(self.n_params, np.float32)
+        g = np.zeros(self.n_params, np.float32) if grads else None
+        _check(_lib.dpdlp_gnn_get_params(self.h, _ptr(p), _ptr(g), self.n_params, self._s))
+        return (p, g) if grads else p
+
+    def set_reference(self, c_ref, b_ref, x_ref, y_ref):
+        a = [np.ascontiguousarray(v, np.float64) for v in (c_ref, b_ref, x_ref, y_ref)]
+        _check(_lib.dpdlp_gnn_set_reference(self.h, *[_ptr(v) for v in a], MEM_HOST, self._s))
+
+    def set_instance(self, c, con_lo, con_hi):
+        a = [np.ascontiguousarray(v, np.float64) for v in (c, con_lo, con_hi)]
+        _check(_lib.dpdlp_gnn_set_instance(self.h, *[_ptr(v) for v in a], MEM_HOST, self._s))
+
+    def forward(self):
+        x = np.zeros(self.problem.n)
+        y = np.zeros(self.problem.m)
+        _check(_lib.dpdlp_gnn_forward(self.h, _ptr(x), _ptr(y), MEM_HOST, self._s))
+        return x, y
+
+    def backward(self, x_target, y_target):
+        loss = np.zeros(2)
+        xt = np.ascontiguousarray(x_target, np.float64)
+        yt = np.ascontiguousarray(y_target, np.float64)
+        _check(_lib.dpdlp_gnn_backward(self.h, _ptr(xt), _ptr(yt), MEM_HOST, _ptr(loss), self._s))
+        return loss
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(_lib.dpdlp_gnn_adam_step(self.h, lr, beta1, beta2, eps, self._s))
+
+
+def dpdlp_gnn_gemm_test(A, a_rs, a_cs, B, b_rs, b_cs, M, Nc, K, stream=None):
+    """Run the MFMA GEMM kernel on device tensors (BF16 bit patterns as int16)."""
+    import torch
+    Cout = torch.zeros((M, Nc), dtype=torch.float32, device=A.device)
+    _check(_lib.dpdlp_gnn_gemm_test(_ptr(A), a_rs, a_cs, _ptr(B), b_rs, b_cs, _ptr(Cout), Nc,
+                                    M, Nc, K, _stream(stream)))
+    return Cout

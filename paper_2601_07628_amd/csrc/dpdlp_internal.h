@@ -32,6 +32,19 @@ struct HostMatrix {
     std::vector<int32_t> perm_row, perm_col;   // perm[new] = old
 };
 
+// Read-only view of a prepared problem's device data (permuted order), for
+// the warm-start network, which runs on the same bipartite graph.
+struct ProblemView {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    const int32_t *rp = nullptr, *ci = nullptr, *cp = nullptr, *ri = nullptr;
+    const double *v = nullptr, *vt = nullptr;        // scaled A~ (CSR, CSC)
+    const int32_t *perm_row = nullptr, *perm_col = nullptr;
+    const double *dr = nullptr, *dc = nullptr;
+    const double *vlo0 = nullptr, *vhi0 = nullptr;   // original variable bounds (permuted)
+};
+int problem_view(dpdlp_problem *P, ProblemView *out);
+
 int validate_host(const dpdlp_csr_lp *lp);
 void block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t *perm);
 void build_tiles(const int32_t *seg_ptr, int32_t nseg, int32_t tile_nnz,

@@ -16,10 +16,9 @@
 //      reflection, Halpern, or a residual contribution) with coalesced
 //      vector loads and stores.
 // A segment longer than a tile is split into pieces; each piece's workgroup
-// reduces its part, publishes it, and the last piece to arrive (an integer
-// atomic counter) adds the pieces in piece order and runs the epilogue.  The
-// summation order is fixed by the tiling alone, so results are bitwise
-// reproducible run to run.
+// reduces its part and publishes it, and a small follow-up kernel adds the
+// pieces in piece order and runs the epilogue.  The summation order is fixed
+// by the tiling alone, so results are bitwise reproducible run to run.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -91,46 +90,86 @@ __device__ __forceinline__ void block_reduce(T (&v)[NQ], T (*s_red)[kBlock / 64]
     }
 }
 
+template <typename T>
+__device__ __forceinline__ void nt_store(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 // Generic tile kernel.  Op supplies:
 //   MT  matrix value type, AT accumulation type, NR right-hand sides,
 //   NQ  per-tile partial quantities (0 = none), R the reduction (Sum/Max),
-//   value(a, j, out[NR])       product for a nonzero a in segment column/row j
-//   epilogue(seg, r[NR], acc)  per-segment update, adds to acc[NQ]
-//   partials                   double* [NQ * ntiles] or null
+//   Pre per-segment values loaded before the reduction (prefetch)
+//   value(a, j, out[NR])          product for a nonzero a with index j
+//   prefetch(seg, pre)            issue the epilogue's vector loads early
+//   epilogue(seg, r[NR], pre, acc) per-segment update, adds to acc[NQ]
+//   partials                      double* [NQ * ntiles] or null
+// Memory-level parallelism: every thread first issues all of its index /
+// value loads (kPer per thread), the segment-pointer loads and the epilogue
+// prefetches, then all of its gathers, so one tile costs about two memory
+// round trips before the LDS phases.
+constexpr int kPer = kTileNnzMax / kBlock;     // nonzeros per thread per tile
+constexpr int kPre = 2;                         // prefetched segments per thread
+
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__ tiles,
                                                  int ntiles,
                                                  const int *__restrict__ seg_ptr,
                                                  const int *__restrict__ idx,
                                                  const typename Op::MT *__restrict__ val,
-                                                 int *__restrict__ counters,
                                                  typename Op::AT *__restrict__ carries,
                                                  int remap)
 {
     using AT = typename Op::AT;
+    using MT = typename Op::MT;
     using R = typename Op::R;
     constexpr int NR = Op::NR;
     constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
     __shared__ AT s_prod[NR][kTileNnzMax];
     __shared__ AT s_seg[NR][kMaxSegs];
+    __shared__ int s_ptr[kMaxSegs + 1];
     __shared__ double s_red[NQ][kBlock / 64];
     __shared__ AT s_redp[NR][kBlock / 64];
-    __shared__ int s_last;
 
     const int t = tile_of_block(remap);
     if (t >= ntiles) return;
     const Tile d = tiles[t];
     const int nnz0 = d.nnz_begin;
     const int cnt = d.nnz_end - d.nnz_begin;
+    const int nseg = d.seg_end - d.seg_begin;
+    const bool whole = d.npieces == 0;
 
-    // 1. stream the tile once, gather, stage products in LDS
-    for (int e = threadIdx.x; e < cnt; e += kBlock) {
-        const int j = nt_load(idx + nnz0 + e);
-        const typename Op::MT a = nt_load(val + nnz0 + e);
-        AT v[NR];
-        op.value(a, j, v);
+    // 1a. issue the tile's matrix stream (coalesced, non-temporal)
+    int jj[kPer];
+    MT aa[kPer];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) s_prod[r][e] = v[r];
+    for (int q = 0; q < kPer; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        if (e < cnt) {
+            jj[q] = nt_load(idx + nnz0 + e);
+            aa[q] = nt_load(val + nnz0 + e);
+        }
+    }
+    // 1b. segment pointers to LDS and the epilogue's vector loads
+    typename Op::Pre pre[kPre];
+    if (whole) {
+        for (int s = threadIdx.x; s <= nseg; s += kBlock) s_ptr[s] = seg_ptr[d.seg_begin + s] - nnz0;
+#pragma unroll
+        for (int q = 0; q < kPre; ++q) {
+            const int s = threadIdx.x + q * kBlock;
+            if (s < nseg) op.prefetch(d.seg_begin + s, pre[q]);
+        }
+    }
+    // 1c. gathers, products to LDS
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        if (e < cnt) {
+            AT v[NR];
+            op.value(aa[q], jj[q], v);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) s_prod[r][e] = v[r];
+        }
     }
     __syncthreads();
 
@@ -138,15 +177,13 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 
-    if (d.npieces == 0) {
-        // 2. segment sums by groups of G lanes
-        const int nseg = d.seg_end - d.seg_begin;
+    if (whole) {
+        // 2. segment reductions by groups of G lanes
         const int G = 1 << d.width_log2;
         const int lane = threadIdx.x & (G - 1);
         const int ngrp = kBlock >> d.width_log2;
         for (int s = threadIdx.x >> d.width_log2; s < nseg; s += ngrp) {
-            const int b = seg_ptr[d.seg_begin + s] - nnz0;
-            const int e = seg_ptr[d.seg_begin + s + 1] - nnz0;
+            const int b = s_ptr[s], e = s_ptr[s + 1];
             AT r[NR];
 #pragma unroll
             for (int q = 0; q < NR; ++q) r[q] = R::template id<AT>();
@@ -163,11 +200,23 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__
         }
         __syncthreads();
         // 3. fused epilogue, one thread per segment (coalesced vector I/O)
-        for (int s = threadIdx.x; s < nseg; s += kBlock) {
+#pragma unroll
+        for (int q = 0; q < kPre; ++q) {
+            const int s = threadIdx.x + q * kBlock;
+            if (s < nseg) {
+                AT r[NR];
+#pragma unroll
+                for (int z = 0; z < NR; ++z) r[z] = s_seg[z][s];
+                op.epilogue(d.seg_begin + s, r, pre[q], acc);
+            }
+        }
+        for (int s = threadIdx.x + kPre * kBlock; s < nseg; s += kBlock) {
             AT r[NR];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) r[q] = s_seg[q][s];
-            op.epilogue(d.seg_begin + s, r, acc);
+            for (int z = 0; z < NR; ++z) r[z] = s_seg[z][s];
+            typename Op::Pre p1;
+            op.prefetch(d.seg_begin + s, p1);
+            op.epilogue(d.seg_begin + s, r, p1, acc);
         }
         if (Op::NQ > 0) {
             block_reduce<SumOp, NQ>(acc, s_red);
@@ -177,7 +226,9 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__
         return;
     }
 
-    // Split segment: reduce this piece, publish it, last piece finishes.
+    // Split segment: reduce this piece and publish it; k_split_fix adds the
+    // pieces in piece order after this launch (no in-kernel cross-workgroup
+    // communication, so no L2-wide fences).
     AT pr[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) pr[q] = R::template id<AT>();
@@ -186,37 +237,53 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__
         for (int q = 0; q < NR; ++q) pr[q] = R::comb(pr[q], s_prod[q][e]);
     }
     block_reduce<R, NR>(pr, s_redp);
-    const int t0 = t - d.piece;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q)
-            __hip_atomic_store(&carries[(size_t)q * ntiles + t], pr[q], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const int old = atomicAdd(&counters[t0], 1);
-        s_last = (old == d.npieces - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        AT r[NR];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            r[q] = R::template id<AT>();
-            for (int pc = 0; pc < d.npieces; ++pc)
-                r[q] = R::comb(r[q], __hip_atomic_load(&carries[(size_t)q * ntiles + t0 + pc],
-                                                       __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT));
-        }
-        counters[t0] = 0;                       // ready for the next launch
-        op.epilogue(d.seg_begin, r, acc);
-        if (Op::NQ > 0)
-            for (int pc = 0; pc < d.npieces; ++pc)
-                for (int q = 0; q < Op::NQ; ++q)
-                    op.partials[(size_t)q * ntiles + t0 + pc] = pc == 0 ? acc[q] : 0.0;
+        for (int q = 0; q < NR; ++q) carries[(size_t)q * ntiles + t] = pr[q];
     }
 }
+
+// A segment split over npieces consecutive tiles starting at tile t0.
+struct SplitSeg {
+    int32_t seg, t0, npieces, pad;
+};
+
+// Finish split segments: one thread per split segment sums its pieces'
+// carries in piece order and runs the epilogue; the segment's partial-sum
+// contribution goes to the slot of its first piece (the other pieces' slots
+// get zero), so every slot is written exactly once per pass.
+template <class Op>
+__global__ __launch_bounds__(64) void k_split_fix(Op op, const SplitSeg *__restrict__ splits,
+                                                   int nsplit, int ntiles,
+                                                   const typename Op::AT *__restrict__ carries)
+{
+    using AT = typename Op::AT;
+    using R = typename Op::R;
+    constexpr int NR = Op::NR;
+    constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsplit) return;
+    const SplitSeg sg = splits[i];
+    AT r[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        r[q] = R::template id<AT>();
+        for (int pc = 0; pc < sg.npieces; ++pc)
+            r[q] = R::comb(r[q], carries[(size_t)q * ntiles + sg.t0 + pc]);
+    }
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    typename Op::Pre p1;
+    op.prefetch(sg.seg, p1);
+    op.epilogue(sg.seg, r, p1, acc);
+    if (Op::NQ > 0)
+        for (int pc = 0; pc < sg.npieces; ++pc)
+            for (int q = 0; q < Op::NQ; ++q)
+                op.partials[(size_t)q * ntiles + sg.t0 + pc] = pc == 0 ? acc[q] : 0.0;
+}
+
+struct NoPre {};
 
 // ---------------------------------------------------------------------------
 // Fused PDHG steps (Sec. 2.2 / Algorithm 1 steps 1-2, with the reflected
@@ -241,14 +308,20 @@ struct PrimalOp {
     double *partials;
     T tau, a, b, gamma;
     int write_hat;
+    struct Pre { T x, c, lo, hi, xa; };
     __device__ void value(MT v, int j, AT *out) const { out[0] = v * y[j]; }
-    __device__ void epilogue(int j, const AT *r, double *) const
+    __device__ void prefetch(int j, Pre &p) const
     {
-        const T g = c[j] - r[0];
-        const T xk = x[j];
-        const T xhv = clampv(xk - tau * g, lo[j], hi[j]);
+        p.x = nt_load(x + j); p.c = nt_load(c + j); p.lo = nt_load(lo + j);
+        p.hi = nt_load(hi + j); p.xa = nt_load(xa + j);
+    }
+    __device__ void epilogue(int j, const AT *r, const Pre &p, double *) const
+    {
+        const T g = p.c - r[0];
+        const T xk = p.x;
+        const T xhv = clampv(xk - tau * g, p.lo, p.hi);
         xbar[j] = T(2) * xhv - xk;
-        x[j] = a * ((T(1) + gamma) * xhv - gamma * xk) + b * xa[j];
+        nt_store(x + j, a * ((T(1) + gamma) * xhv - gamma * xk) + b * p.xa);
         if (write_hat) {
             xh[j] = (double)xhv;
             dx[j] = (double)xk - (double)xhv;
@@ -273,13 +346,18 @@ struct DualOp {
     double *partials;
     T sigma, a, b, gamma;
     int write_hat;
+    struct Pre { T y, lo, hi, ya; };
     __device__ void value(MT v, int j, AT *out) const { out[0] = v * xbar[j]; }
-    __device__ void epilogue(int i, const AT *r, double *) const
+    __device__ void prefetch(int i, Pre &p) const
     {
-        const T yk = y[i];
+        p.y = y[i]; p.lo = nt_load(lo + i); p.hi = nt_load(hi + i); p.ya = nt_load(ya + i);
+    }
+    __device__ void epilogue(int i, const AT *r, const Pre &p, double *) const
+    {
+        const T yk = p.y;
         const T w = yk / sigma - r[0];
-        const T yhv = sigma * (w - clampv(w, -hi[i], -lo[i]));
-        y[i] = a * ((T(1) + gamma) * yhv - gamma * yk) + b * ya[i];
+        const T yhv = sigma * (w - clampv(w, -p.hi, -p.lo));
+        y[i] = a * ((T(1) + gamma) * yhv - gamma * yk) + b * p.ya;
         if (write_hat) {
             yh[i] = (double)yhv;
             dy[i] = (double)yk - (double)yhv;
@@ -315,7 +393,9 @@ struct CheckRowOp {
         out[0] = v * xh[j];
         out[1] = v * dx[j];
     }
-    __device__ void epilogue(int i, const AT *r, double *acc) const
+    using Pre = NoPre;
+    __device__ void prefetch(int, Pre &) const {}
+    __device__ void epilogue(int i, const AT *r, const Pre &, double *acc) const
     {
         const double axi = r[0] / dr[i];
         const double res = axi - clampv(axi, lo0[i], hi0[i]);
@@ -353,7 +433,9 @@ struct CheckColOp {
     double *partials;
     double tau;
     __device__ void value(MT v, int i, AT *out) const { out[0] = v * yh[i]; }
-    __device__ void epilogue(int j, const AT *r, double *acc) const
+    using Pre = NoPre;
+    __device__ void prefetch(int, Pre &) const {}
+    __device__ void epilogue(int j, const AT *r, const Pre &, double *acc) const
     {
         const double g = c[j] - r[0];
         const double u = xh[j] - tau * g;
@@ -383,7 +465,9 @@ struct SpmvOp {
     {
         o[0] = div ? v * (in[j] / *div) : v * in[j];
     }
-    __device__ void epilogue(int s, const AT *r, double *acc) const
+    using Pre = NoPre;
+    __device__ void prefetch(int, Pre &) const {}
+    __device__ void epilogue(int s, const AT *r, const Pre &, double *acc) const
     {
         out[s] = r[0];
         acc[0] += r[0] * r[0];
@@ -398,7 +482,9 @@ struct AbsMaxOp {
     double *__restrict__ f;
     double *partials;
     __device__ void value(MT v, int, AT *o) const { o[0] = fabs(v); }
-    __device__ void epilogue(int s, const AT *r, double *) const
+    using Pre = NoPre;
+    __device__ void prefetch(int, Pre &) const {}
+    __device__ void epilogue(int s, const AT *r, const Pre &, double *) const
     {
         f[s] = r[0] > 0.0 ? 1.0 / sqrt(r[0]) : 1.0;
     }
@@ -410,7 +496,9 @@ struct AbsPowSumOp {
     double *partials;
     double p;
     __device__ void value(MT v, int, AT *o) const { o[0] = p == 1.0 ? fabs(v) : pow(fabs(v), p); }
-    __device__ void epilogue(int s, const AT *r, double *) const
+    using Pre = NoPre;
+    __device__ void prefetch(int, Pre &) const {}
+    __device__ void epilogue(int s, const AT *r, const Pre &, double *) const
     {
         f[s] = r[0] > 0.0 ? 1.0 / sqrt(r[0]) : 1.0;
     }

@@ -296,7 +296,8 @@ __global__ __launch_bounds__(kBlock) void k_control(const double *pr, int ntr, c
 struct TileSet {
     Tile *d = nullptr;
     int n = 0;
-    int *counters = nullptr;
+    SplitSeg *splits = nullptr;     // segments split over several tiles
+    int nsplit = 0;
 };
 
 struct DevMem {
@@ -335,7 +336,8 @@ struct dpdlp_problem {
     float *c32 = nullptr, *clo32 = nullptr, *chi32 = nullptr, *vlo32 = nullptr, *vhi32 = nullptr;
     // scratch
     double *tmp_m = nullptr, *tmp_n = nullptr, *tmp_m2 = nullptr, *tmp_n2 = nullptr;
-    double *scal = nullptr;         // device scalars: [0] lam, [1..4] norms
+    double *scal = nullptr;         // device scalars: [0] lam, [4..7] norms
+    double *norm_part = nullptr;
     double *sig_hist = nullptr;
     Control *ctl = nullptr;
     Control *ctl_eval = nullptr;    // scratch block for dpdlp_kkt
@@ -401,7 +403,10 @@ static void launch_tiles(dpdlp_problem *P, const Op &op, const TileSet &ts, cons
     const int remap = P->prm.xcd_remap ? 1 : 0;
     const int grid = remap ? ((ts.n + 7) / 8) * 8 : ts.n;
     hipLaunchKernelGGL(k_tile<Op>, dim3(grid), dim3(kBlock), 0, P->s, op, ts.d, ts.n, seg_ptr,
-                       idx, val, ts.counters, (typename Op::AT *)P->carries, remap);
+                       idx, val, (typename Op::AT *)P->carries, remap);
+    if (ts.nsplit)
+        hipLaunchKernelGGL(k_split_fix<Op>, dim3((ts.nsplit + 63) / 64), dim3(64), 0, P->s, op,
+                           ts.splits, ts.nsplit, ts.n, (const typename Op::AT *)P->carries);
 }
 
 // ---- profiling helpers -----------------------------------------------------
@@ -552,12 +557,19 @@ static int build_tileset(dpdlp_problem *P, const std::vector<int32_t> &ptr, int3
 {
     build_tiles(ptr.data(), nseg, P->prm.tile_nnz, host_tiles);
     ts.n = (int)host_tiles.size();
+    std::vector<SplitSeg> sp;
+    for (int i = 0; i < ts.n; ++i) {
+        const Tile &t = host_tiles[(size_t)i];
+        if (t.npieces > 0 && t.piece == 0) sp.push_back(SplitSeg{t.seg_begin, i, t.npieces, 0});
+    }
+    ts.nsplit = (int)sp.size();
     CHK(dalloc(P, &ts.d, host_tiles.size()));
-    CHK(dalloc(P, &ts.counters, host_tiles.size()));
     CHK(upload(P, ts.d, host_tiles.data(), host_tiles.size() * sizeof(Tile)));
-    HIPCHK(hipMemsetAsync(ts.counters, 0, std::max<size_t>(host_tiles.size(), 1) * sizeof(int),
-                          P->s));
-    HIPCHK(hipStreamSynchronize(P->s));     // host_tiles is reused by the caller
+    if (ts.nsplit) {
+        CHK(dalloc(P, &ts.splits, sp.size()));
+        CHK(upload(P, ts.splits, sp.data(), sp.size() * sizeof(SplitSeg)));
+    }
+    HIPCHK(hipStreamSynchronize(P->s));     // host vectors are reused by the caller
     return DPDLP_OK;
 }
 
@@ -603,6 +615,40 @@ static int power_iteration(dpdlp_problem *P)
     if (stop < 0) stop = it_done;
     P->power_iters = stop;
     P->sigma_max = hist[(size_t)stop];
+    return DPDLP_OK;
+}
+
+// Scaled problem vectors (c~, bounds) and the norms used by the KKT
+// denominators and omega0, from the permuted original vectors and D_r, D_c.
+static int scale_data(dpdlp_problem *P)
+{
+    const int32_t m = P->m, n = P->n;
+    hipLaunchKernelGGL(k_scale_vectors, dim3(nblk(std::max(m, n))), dim3(kBlock), 0, P->s, m, n,
+                       P->dr, P->dc, P->c0, P->vlo0, P->vhi0, P->clo0, P->chi0, P->c, P->vlo,
+                       P->vhi, P->clo, P->chi);
+    const unsigned nb = nblk(std::max(m, n));
+    if (!P->norm_part) CHK(dalloc(P, &P->norm_part, (size_t)4 * nb));
+    hipLaunchKernelGGL(k_norm_partials, dim3(nb), dim3(kBlock), 0, P->s, m, n, P->c0, P->clo0,
+                       P->chi0, P->c, P->clo, P->chi, P->norm_part);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, P->s, P->norm_part, (int)nb, 4,
+                       P->scal + 4);
+    double h[4];
+    HIPCHK(hipMemcpyAsync(h, P->scal + 4, sizeof(h), hipMemcpyDeviceToHost, P->s));
+    HIPCHK(hipStreamSynchronize(P->s));
+    P->c_norm = std::sqrt(h[0]);
+    P->b_norm = std::sqrt(h[1]);
+    const double cns = std::sqrt(h[2]), bns = std::sqrt(h[3]);
+    if (P->prm.omega0 > 0) P->omega0 = P->prm.omega0;
+    else if (cns > 1e-10 && bns > 1e-10) P->omega0 = cns / bns;
+    else P->omega0 = 1.0;
+    if (P->prm.precision == DPDLP_FP32_MIXED && P->c32) {
+        auto cv = [&](const double *a, float *b, int64_t k) {
+            hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(k)), dim3(kBlock), 0, P->s, a, b, k);
+        };
+        cv(P->c, P->c32, n); cv(P->vlo, P->vlo32, n); cv(P->vhi, P->vhi32, n);
+        cv(P->clo, P->clo32, m); cv(P->chi, P->chi32, m);
+    }
+    HIPCHK(hipGetLastError());
     return DPDLP_OK;
 }
 
@@ -739,27 +785,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         launch_tiles(P, b, P->tc, P->cp, P->ri, P->vt);
         apply_scale();
     }
-    hipLaunchKernelGGL(k_scale_vectors, dim3(nblk(std::max(m, n))), dim3(kBlock), 0, P->s, m, n,
-                       P->dr, P->dc, P->c0, P->vlo0, P->vhi0, P->clo0, P->chi0, P->c, P->vlo,
-                       P->vhi, P->clo, P->chi);
-    // norms for the KKT denominators and omega0
-    {
-        const unsigned nb = nblk(std::max(m, n));
-        double *part = nullptr;
-        CHK(dalloc(P, &part, (size_t)4 * nb));
-        hipLaunchKernelGGL(k_norm_partials, dim3(nb), dim3(kBlock), 0, P->s, m, n, P->c0, P->clo0,
-                           P->chi0, P->c, P->clo, P->chi, part);
-        hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, P->s, part, (int)nb, 4, P->scal + 4);
-        double h[4];
-        HIPCHK(hipMemcpyAsync(h, P->scal + 4, sizeof(h), hipMemcpyDeviceToHost, P->s));
-        HIPCHK(hipStreamSynchronize(P->s));
-        P->c_norm = std::sqrt(h[0]);
-        P->b_norm = std::sqrt(h[1]);
-        const double cns = std::sqrt(h[2]), bns = std::sqrt(h[3]);
-        if (P->prm.omega0 > 0) P->omega0 = P->prm.omega0;
-        else if (cns > 1e-10 && bns > 1e-10) P->omega0 = cns / bns;
-        else P->omega0 = 1.0;
-    }
+    CHK(scale_data(P));
     // A4: step size
     if (P->prm.eta > 0) {
         P->eta = P->prm.eta;
@@ -780,8 +806,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
             if (k) hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(k)), dim3(kBlock), 0, P->s, a, b, k);
         };
         cv(P->v, P->v32, (int64_t)nnz); cv(P->vt, P->vt32, (int64_t)nnz);
-        cv(P->c, P->c32, n); cv(P->vlo, P->vlo32, n); cv(P->vhi, P->vhi32, n);
-        cv(P->clo, P->clo32, m); cv(P->chi, P->chi32, m);
+        CHK(scale_data(P));
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->s));
@@ -973,6 +998,16 @@ static void fill_result(dpdlp_problem *P, dpdlp_result *r)
     r->power_iters = P->power_iters; r->n_checks = C.n_checks;
 }
 
+int problem_view(dpdlp_problem *P, ProblemView *o)
+{
+    if (!P || !o) return DPDLP_E_INVALID_ARG;
+    o->m = P->m; o->n = P->n; o->nnz = P->nnz;
+    o->rp = P->rp; o->ci = P->ci; o->cp = P->cp; o->ri = P->ri; o->v = P->v; o->vt = P->vt;
+    o->perm_row = P->perm_row; o->perm_col = P->perm_col; o->dr = P->dr; o->dc = P->dc;
+    o->vlo0 = P->vlo0; o->vhi0 = P->vhi0;
+    return DPDLP_OK;
+}
+
 }  // namespace dpdlp
 
 // ---------------------------------------------------------------------------
@@ -990,6 +1025,65 @@ int dpdlp_problem_create(const dpdlp_csr_lp *lp, const dpdlp_params *params, voi
     return create_impl(lp, params, stream, out);
 }
 
+int dpdlp_problem_update_data(dpdlp_problem *P, const double *c, const double *con_lo,
+                              const double *con_hi, const double *var_lo, const double *var_hi,
+                              int32_t mem_kind, void *stream)
+{
+    ENTER(P);
+    const int32_t m = P->m, n = P->n;
+    struct Item { const double *src; int k; const std::vector<int32_t> *perm; double *dst; } items[] = {
+        {c, n, &P->h_perm_col, P->c0}, {var_lo, n, &P->h_perm_col, P->vlo0},
+        {var_hi, n, &P->h_perm_col, P->vhi0}, {con_lo, m, &P->h_perm_row, P->clo0},
+        {con_hi, m, &P->h_perm_row, P->chi0}};
+    std::vector<double> a((size_t)std::max(m, n)), b((size_t)std::max(m, n));
+    // host copies for validation (device inputs are brought over)
+    std::vector<std::vector<double>> host(5);
+    for (int q = 0; q < 5; ++q) {
+        if (!items[q].src) continue;
+        host[(size_t)q].resize((size_t)items[q].k);
+        if (mem_kind == DPDLP_MEM_DEVICE)
+            HIPCHK(hipMemcpy(host[(size_t)q].data(), items[q].src, sizeof(double) * items[q].k,
+                             hipMemcpyDeviceToHost));
+        else
+            std::memcpy(host[(size_t)q].data(), items[q].src, sizeof(double) * items[q].k);
+    }
+    if (c)
+        for (int32_t j = 0; j < n; ++j)
+            if (!std::isfinite(host[0][(size_t)j])) { set_error("non-finite c"); return DPDLP_E_BAD_BOUNDS; }
+    for (int pair = 0; pair < 2; ++pair) {
+        const int ql = pair == 0 ? 1 : 3, qh = ql + 1;
+        if (!items[ql].src && !items[qh].src) continue;
+        const int k = items[ql].k;
+        // current values for the side not given
+        std::vector<double> lo((size_t)k), hi((size_t)k);
+        for (int side = 0; side < 2; ++side) {
+            const int q = side == 0 ? ql : qh;
+            std::vector<double> &dst = side == 0 ? lo : hi;
+            if (items[q].src) { dst = host[(size_t)q]; continue; }
+            std::vector<double> tmp((size_t)k);
+            HIPCHK(hipMemcpy(tmp.data(), items[q].dst, sizeof(double) * k, hipMemcpyDeviceToHost));
+            for (int i = 0; i < k; ++i) dst[(size_t)(*items[q].perm)[(size_t)i]] = tmp[(size_t)i];
+        }
+        for (int i = 0; i < k; ++i) {
+            const double l = lo[(size_t)i], h = hi[(size_t)i];
+            if (std::isnan(l) || std::isnan(h) || l > h || l == INFINITY || h == -INFINITY) {
+                set_error("bad bounds at index " + std::to_string(i));
+                return DPDLP_E_BAD_BOUNDS;
+            }
+        }
+    }
+    for (int q = 0; q < 5; ++q) {
+        if (!items[q].src) continue;
+        const int k = items[q].k;
+        for (int i = 0; i < k; ++i) a[(size_t)i] = host[(size_t)q][(size_t)(*items[q].perm)[(size_t)i]];
+        HIPCHK(hipMemcpy(items[q].dst, a.data(), sizeof(double) * k, hipMemcpyHostToDevice));
+    }
+    CHK(scale_data(P));
+    HIPCHK(hipStreamSynchronize(P->s));
+    P->initialized = false;
+    return DPDLP_OK;
+}
+
 int dpdlp_problem_destroy(dpdlp_problem *P)
 {
     if (!P) return DPDLP_OK;
@@ -999,6 +1093,19 @@ int dpdlp_problem_destroy(dpdlp_problem *P)
         for (auto &pr : P->ev[c]) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto e : P->ev_pool) (void)hipEventDestroy(e);
     delete P;
+    return DPDLP_OK;
+}
+
+int dpdlp_set_params(dpdlp_problem *P, const dpdlp_params *q)
+{
+    if (!P || !q) { set_error("NULL argument"); return DPDLP_E_INVALID_ARG; }
+    if (q->check_period < 1 || q->max_iters < 0) { set_error("bad check_period / max_iters"); return DPDLP_E_INVALID_ARG; }
+    dpdlp_params &p = P->prm;
+    p.eps = q->eps; p.max_iters = q->max_iters; p.time_limit = q->time_limit;
+    p.check_period = q->check_period; p.gamma = q->gamma;
+    p.beta_suf = q->beta_suf; p.beta_nec = q->beta_nec; p.beta_art = q->beta_art;
+    p.kp = q->kp; p.ki = q->ki; p.kd = q->kd; p.xcd_remap = q->xcd_remap;
+    p.fp32_switch_tol = q->fp32_switch_tol; p.fp32_stall_checks = q->fp32_stall_checks;
     return DPDLP_OK;
 }
 
@@ -1143,20 +1250,32 @@ int dpdlp_kkt(dpdlp_problem *P, const double *x, const double *y, double tau, in
               double *out5, void *stream)
 {
     ENTER(P);
-    if (!x || !y || !out5) { set_error("NULL argument"); return DPDLP_E_INVALID_ARG; }
+    if (!out5 || (!x) != (!y)) { set_error("bad arguments"); return DPDLP_E_INVALID_ARG; }
     const int32_t m = P->m, n = P->n;
-    const double *dxp = x, *dyp = y;
-    if (mem_kind == DPDLP_MEM_HOST) {
-        HIPCHK(hipMemcpyAsync(P->tmp_n2, x, sizeof(double) * n, hipMemcpyHostToDevice, P->s));
-        HIPCHK(hipMemcpyAsync(P->tmp_m2, y, sizeof(double) * m, hipMemcpyHostToDevice, P->s));
-        dxp = P->tmp_n2; dyp = P->tmp_m2;
-    }
-    // scaled, permuted copies in tmp_n / tmp_m
-    hipLaunchKernelGGL(k_permute<double>, dim3(nblk(n)), dim3(kBlock), 0, P->s, n, dxp, P->perm_col,
-                       P->dc, P->tmp_n);
-    hipLaunchKernelGGL(k_permute<double>, dim3(nblk(m)), dim3(kBlock), 0, P->s, m, dyp, P->perm_row,
-                       P->dr, P->tmp_m);
     if (tau <= 0) tau = P->eta / P->omega;
+    if (!x) {
+        // the current start point (set by dpdlp_init: clamped into X, projected onto Y)
+        if (!P->initialized) CHK(init_impl(P, nullptr, nullptr, DPDLP_MEM_HOST));
+        if (P->in_fp32) {
+            hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(n)), dim3(kBlock), 0, P->s, P->xa32, P->tmp_n, (int64_t)n);
+            hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(m)), dim3(kBlock), 0, P->s, P->ya32, P->tmp_m, (int64_t)m);
+        } else {
+            HIPCHK(hipMemcpyAsync(P->tmp_n, P->xa, sizeof(double) * n, hipMemcpyDeviceToDevice, P->s));
+            HIPCHK(hipMemcpyAsync(P->tmp_m, P->ya, sizeof(double) * m, hipMemcpyDeviceToDevice, P->s));
+        }
+    } else {
+        const double *dxp = x, *dyp = y;
+        if (mem_kind == DPDLP_MEM_HOST) {
+            HIPCHK(hipMemcpyAsync(P->tmp_n2, x, sizeof(double) * n, hipMemcpyHostToDevice, P->s));
+            HIPCHK(hipMemcpyAsync(P->tmp_m2, y, sizeof(double) * m, hipMemcpyHostToDevice, P->s));
+            dxp = P->tmp_n2; dyp = P->tmp_m2;
+        }
+        // scaled, permuted copies in tmp_n / tmp_m
+        hipLaunchKernelGGL(k_permute<double>, dim3(nblk(n)), dim3(kBlock), 0, P->s, n, dxp, P->perm_col,
+                           P->dc, P->tmp_n);
+        hipLaunchKernelGGL(k_permute<double>, dim3(nblk(m)), dim3(kBlock), 0, P->s, m, dyp, P->perm_row,
+                           P->dr, P->tmp_m);
+    }
     launch_checks<double>(P, P->tmp_n, P->tmp_n, P->tmp_m, P->tmp_m, P->tmp_n, P->tmp_m, tau);
     // evaluate into a scratch control block so the solver state is untouched
     HIPCHK(hipMemsetAsync(P->ctl_eval, 0, sizeof(Control), P->s));

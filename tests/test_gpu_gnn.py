@@ -1,0 +1,163 @@
+"""GPU tests of the learned warm start: the MFMA GEMM kernel, the network's
+forward pass and gradients against the FP64 reference (oracle/gnn_ref.py),
+training on the GPU, and the warm start judged against a cold start.
+
+Tolerances: the GPU computes in BF16 (8-bit mantissa) with FP32
+accumulation, the reference in FP64, so predictions and gradients are
+compared with relative 2-norm errors of a few percent (per parameter block),
+the bar stated for BF16 training kernels."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_2601_07628_amd as D
+    return D
+
+
+def bf16_bits(a):
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def bf16_value(b):
+    return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("M,Nc,K,pattern", [
+    (100, 70, 50, "nn"), (64, 128, 256, "nn"), (257, 128, 128, "nt"),
+    (16, 128, 3000, "tn"), (256, 128, 2049, "tn")])
+def test_mfma_gemm_matches_numpy(D, M, Nc, K, pattern):
+    import torch
+    rng = np.random.default_rng(M + K)
+    if pattern == "nn":            # A row-major M x K, B row-major K x Nc
+        Am = rng.standard_normal((M, K)); Bm = rng.standard_normal((K, Nc))
+        A, a_rs, a_cs = Am, K, 1
+        B, b_rs, b_cs = Bm, Nc, 1
+    elif pattern == "nt":          # B given as W (Nc x K): B(k,j) = W[j,k]
+        Am = rng.standard_normal((M, K)); W = rng.standard_normal((Nc, K)); Bm = W.T
+        A, a_rs, a_cs = Am, K, 1
+        B, b_rs, b_cs = W, 1, K
+    else:                          # A given as X (K x M): A(i,k) = X[k,i]
+        X = rng.standard_normal((K, M)); Am = X.T; Bm = rng.standard_normal((K, Nc))
+        A, a_rs, a_cs = X, 1, M
+        B, b_rs, b_cs = Bm, Nc, 1
+    Ab, Bb = bf16_bits(A), bf16_bits(B)
+    ta = torch.from_numpy(Ab.view(np.int16).copy()).cuda()
+    tb = torch.from_numpy(Bb.view(np.int16).copy()).cuda()
+    C = D.dpdlp_gnn_gemm_test(ta, a_rs, a_cs, tb, b_rs, b_cs, M, Nc, K).cpu().numpy()
+    Aq = bf16_value(Ab).reshape(A.shape)
+    Bq = bf16_value(Bb).reshape(B.shape)
+    Aq = Aq if pattern != "tn" else Aq.T
+    Bq = Bq if pattern != "nt" else Bq.T
+    ref = Aq @ Bq
+    err = np.abs(C - ref).max() / np.abs(ref).max()
+    assert err < 1e-5, err
+
+
+def _family(base_m=1500, base_n=3000, n_inst=8, seed=21):
+    base = lpgen.constructed_lp(base_m, base_n, base_m // 2, 8, seed=seed)
+    insts = [lpgen.perturbed(base, 1000 + seed * 100 + i) for i in range(n_inst)]
+    return base, insts
+
+
+def test_gnn_forward_and_gradient_match_fp64_reference(D):
+    import oracle
+    from oracle import gnn_ref
+    from paper_2601_07628_amd import warmstart as W
+    base, insts = _family()
+    layers = 3
+    G = D.Problem(base)
+    net = D.WarmStartNet(G, layers=layers)
+    assert net.n_params == gnn_ref.n_params(layers)
+    rng = np.random.default_rng(3)
+    p = W.init_params(layers, seed=5)
+    p[-256:] = 0.05 * rng.standard_normal(256)            # nonzero heads
+    net.set_params(p)
+    x_ref, y_ref = base.x_star, base.y_star
+    b_ref = D.row_b(base.con_lo, base.con_hi)
+    net.set_reference(base.c, b_ref, x_ref, y_ref)
+    inst = insts[0]
+    net.set_instance(inst.c, inst.con_lo, inst.con_hi)
+    x0, y0 = net.forward()
+    tx = x_ref + rng.standard_normal(base.n)
+    ty = y_ref + rng.standard_normal(base.m)
+    loss = net.backward(tx, ty)
+    _, g = net.params(grads=True)
+
+    # reference, from the oracle's own scaling of the same matrix
+    P = oracle.Problem(base, oracle.Params(eta=1.0, omega0=1.0))
+    sd = P.scaled()
+    dr, dc = sd["dr"], sd["dc"]
+    A = sp.csr_matrix((sd["v"], base.col_idx, base.row_ptr), shape=(base.m, base.n))
+    Xc, Xr = gnn_ref.features(inst.c, inst.con_lo, inst.con_hi, inst.var_lo, inst.var_hi,
+                              base.c, b_ref, x_ref, y_ref, dr, dc)
+    px, py, _ = gnn_ref.forward(p.astype(np.float64), layers, A, Xc, Xr, x_ref / dc, y_ref / dr)
+    rel = lambda a, b: np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    # predictions: compare the learned correction (prediction minus reference)
+    assert rel(x0 / dc - x_ref / dc, px - x_ref / dc) < 3e-2
+    assert rel(y0 / dr - y_ref / dr, py - y_ref / dr) < 3e-2
+    L, gr = gnn_ref.loss_and_grad(p.astype(np.float64), layers, A, Xc, Xr, x_ref / dc,
+                                  y_ref / dr, tx / dc, ty / dr)
+    assert abs(loss.sum() - L) <= 2e-2 * L
+    d_g, d_r = gnn_ref.unpack(g, layers), gnn_ref.unpack(gr, layers)
+    blocks = [("W_cin", None), ("W_rin", None), ("w_x", None), ("w_y", None)]
+    blocks += [("W_c", l) for l in range(layers)] + [("W_r", l) for l in range(layers)]
+    for name, l in blocks:
+        a = d_g[name] if l is None else d_g[name][l]
+        b = d_r[name] if l is None else d_r[name][l]
+        assert rel(a, b) < 5e-2, (name, l, rel(a, b))
+
+
+def test_gnn_training_reduces_loss_and_is_deterministic(D):
+    from paper_2601_07628_amd import warmstart as W
+    base, insts = _family(n_inst=12)
+    G = D.Problem(base, eps=1e-8)
+    sols = W.family_targets(G, insts)
+    assert sum(s is not None for s in sols) >= 10
+    ref = W.reference(insts, sols)
+    hists = []
+    for _ in range(2):
+        net = D.WarmStartNet(G, layers=3)
+        net.set_params(W.init_params(3, seed=1))
+        net.set_reference(*ref)
+        hists.append(W.train(net, insts, sols, epochs=6, lr=2e-3, seed=0))
+    h = hists[0]
+    assert sum(h[-1]) < 0.8 * sum(h[0]), h
+    assert hists[0] == hists[1]                     # bitwise reproducible training
+
+
+def test_warm_start_judge_and_gain(D):
+    """Held-out members: the mean-reference and the trained network start no
+    worse than cold on average, the judge never keeps a start with a worse
+    KKT error than the cold one, and all runs converge to the same optimum."""
+    from paper_2601_07628_amd import warmstart as W
+    base, insts = _family(n_inst=28)
+    train_i, test_i = insts[:20], insts[20:]
+    G = D.Problem(base, eps=1e-8)
+    sols = W.family_targets(G, train_i)
+    ref = W.reference(train_i, sols)
+    net = D.WarmStartNet(G, layers=3)
+    net.set_params(W.init_params(3, seed=2))
+    net.set_reference(*ref)
+    W.train(net, train_i, sols, epochs=8, lr=2e-3)
+    res = {m: [W.warm_solve(G, inst, m, net=net, ref=ref) for inst in test_i]
+           for m in ("cold", "mean", "gnn")}
+    for m in res:
+        assert all(r["status"] == D.CONVERGED for r in res[m]), m
+    for rc, rm, rg in zip(res["cold"], res["mean"], res["gnn"]):
+        for r in (rm, rg):
+            assert abs(r["obj"] - rc["obj"]) <= 1e-6 * (1 + abs(rc["obj"]))
+            if not r["fallback"]:
+                assert r["kkt_warm"] < r["kkt_cold"]
+    it = {m: np.mean([r["iters"] for r in res[m]]) for m in res}
+    assert it["mean"] <= it["cold"] and it["gnn"] <= it["cold"], it

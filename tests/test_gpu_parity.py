@@ -91,9 +91,13 @@ def fixed_run(D, O, lp, n_iters, gpu_kw=None, ora_kw=None, tol=1e-10):
         assert gs["scalars"]["t"] == st["state"].t
         assert gs["scalars"]["k"] == st["state"].k
         # omega comes out of log(omega dx/dy) with dx, dy the distances to the
-        # anchor; near convergence those are differences of nearly equal
-        # vectors, so a 1e-16 rounding difference can move omega by ~1e-8.
-        assert np.isclose(gs["scalars"]["omega"], st["state"].omega, rtol=1e-6)
+        # anchor.  Once the iterate has converged to rounding level those are
+        # differences of nearly equal vectors and omega follows rounding noise
+        # (the iterate no longer depends on it), so omega is compared only
+        # while the last check's KKT error is above that level.
+        last = st["log"][-1] if st["log"] else None
+        if last is not None and max(last["r_primal"], last["r_dual"], last["r_gap"]) > 1e-11:
+            assert np.isclose(gs["scalars"]["omega"], st["state"].omega, rtol=1e-6)
     return G, P, st, gs, same
 
 
@@ -118,7 +122,6 @@ def test_spmv_matches_oracle(D, O, transpose):
     out = G.spmv(torch.from_numpy(v).cuda(), transpose=transpose).cpu().numpy()
     ref = P.spmv(v, transpose=transpose)
     # element-wise: each entry is the same sum in another order
-    scale = np.abs(P.spmv(np.abs(v), transpose=transpose)) if False else None
     assert np.allclose(out, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
@@ -159,9 +162,7 @@ def test_kkt_matches_oracle(D, O):
     ("transport-60x4000", lambda: lpgen.transport_lp(60, 4000, seed=3), 400),
 ])
 def test_iterate_parity(D, O, name, maker, n_iters):
-    lp = maker()
-    _, _, _, _, same = fixed_run(D, O, lp, n_iters)
-    assert same or True
+    fixed_run(D, O, maker(), n_iters)
 
 
 @pytest.mark.parametrize("remap,block", [(0, 256), (1, 0)])
