@@ -119,6 +119,50 @@ def time_to_tol(D, lp, torch, **kw):
     return out
 
 
+def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3):
+    """Config-4 family: targets from the FP64 solver, network trained on the
+    GPU, held-out members solved cold / from the mean solution / from the
+    network (with the KKT-judged fallback) to 1e-6 and 1e-8."""
+    import numpy as np
+    import lpgen
+    from paper_2601_07628_amd import warmstart as W
+    base = lpgen.config4()
+    insts = [lpgen.config4_family(i, base) for i in range(n_train + n_test)]
+    train_i, test_i = insts[:n_train], insts[n_train:]
+    G = D.Problem(base, gpu_params(D, eps=1e-8, max_iters=200000),
+                  stream=torch.cuda.current_stream())
+    t0 = time.perf_counter()
+    sols = W.family_targets(G, train_i, log=log)
+    t_targets = time.perf_counter() - t0
+    ok = sum(s is not None for s in sols)
+    ref = W.reference(train_i, sols)
+    net = D.WarmStartNet(G, layers=3, stream=torch.cuda.current_stream())
+    net.set_params(W.init_params(3, seed=0))
+    net.set_reference(*ref)
+    t0 = time.perf_counter()
+    hist = W.train(net, train_i, sols, epochs=epochs, lr=lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    out = {"train_instances": n_train, "targets_converged": ok, "held_out": n_test,
+           "targets_seconds": round(t_targets, 2), "train_seconds": round(t_train, 2),
+           "epochs": epochs, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    for eps in (1e-6, 1e-8):
+        G.set_params(eps=eps)
+        row = {}
+        for mode in ("cold", "mean", "gnn"):
+            rs = [W.warm_solve(G, inst, mode, net=net, ref=ref) for inst in test_i]
+            conv = [r for r in rs if r["status"] == D.CONVERGED]
+            row[mode] = {"mean_iters": round(float(np.mean([r["iters"] for r in rs])), 1),
+                         "mean_ms": round(1e3 * float(np.mean([r["seconds"] for r in rs])), 3),
+                         "converged": len(conv),
+                         "fallbacks": int(sum(r["fallback"] for r in rs))}
+        out[f"eps_{eps:g}"] = row
+        log(f"warm start eps={eps:g}: {row}")
+    net.close()
+    G.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +172,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 256 MiB buffer (device to device), a kernel of "
                          "known size that calibrates the HBM byte counters")
@@ -205,6 +250,21 @@ def main():
     del G
 
     if not args.no_extra:
+        for S in (8, 16):
+            GS = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9, gather_slices=S),
+                           stream=stream)
+            GS.init()
+            GS.iterate(ips)
+            GS.profile_enable(True)
+            elS = timed_steps(GS, max(5, args.steps // 2), ips, torch)
+            pS = GS.profile()
+            extra[f"fp64_xcd_sliced_{S}"] = {
+                "iters_per_s": round(max(5, args.steps // 2) * ips / elS, 1),
+                "primal_ms": round(pS["primal"]["total_ms"] / max(pS["primal"]["launches"], 1), 4),
+                "dual_ms": round(pS["dual"]["total_ms"] / max(pS["dual"]["launches"], 1), 4)}
+            log(f"FP64 XCD-sliced S={S}: {extra[f'fp64_xcd_sliced_{S}']}")
+            GS.close()
+            del GS
         G32 = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9,
                                         precision=D.FP32_MIXED, fp32_stall_checks=10**6,
                                         fp32_switch_tol=0.0), stream=stream)
@@ -224,6 +284,9 @@ def main():
                 "fp64": time_to_tol(D, inst, torch),
                 "fp32_mixed": time_to_tol(D, inst, torch, precision=D.FP32_MIXED)}
             log(f"time-to-tolerance {name}: {extra[f'time_to_tol_{name}']}")
+
+    if not args.no_extra and not args.no_warmstart:
+        extra["warm_start_c4"] = warmstart_eval(D, torch)
 
     cpu = None
     if not args.no_cpu:

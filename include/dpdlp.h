@@ -94,7 +94,11 @@ typedef struct dpdlp_params {
     int32_t xcd_remap;        /* 1: map consecutive tiles onto one XCD        */
     double fp32_switch_tol;   /* FP32 -> FP64 switch when KKT <= this (1e-6) */
     int32_t fp32_stall_checks;/* ... or no 2x KKT improvement in this many checks (8) */
-    int32_t pad0;
+    int32_t gather_slices;    /* 0: off; S (multiple of 8, <= 64): cut the    */
+                              /* gathered dimension of each fused step into S */
+                              /* slices, slice s on XCD s % 8, partial sums   */
+                              /* added per segment in slice order (the 2-D    */
+                              /* partition of Sec. 3.1 across the 8 XCDs)     */
 } dpdlp_params;
 
 typedef struct dpdlp_result {

@@ -54,10 +54,10 @@ class Params(C.Structure):
                 ("tile_nnz", C.c_int32), ("perm_seed", C.c_uint64),
                 ("precision", C.c_int32), ("xcd_remap", C.c_int32),
                 ("fp32_switch_tol", C.c_double), ("fp32_stall_checks", C.c_int32),
-                ("pad0", C.c_int32)]
+                ("gather_slices", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Result(C.Structure):

@@ -160,6 +160,44 @@ void build_tiles(const int32_t *ptr, int32_t nseg, int32_t tile_nnz,
     }
 }
 
+void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                  int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out)
+{
+    out.S = S;
+    out.size = (nidx + S - 1) / S;
+    const int64_t nnz = ptr[(size_t)nseg];
+    // count per (slice, segment)
+    std::vector<int64_t> cnt((size_t)S * (size_t)(nseg + 1), 0);
+    for (int32_t g = 0; g < nseg; ++g)
+        for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p)
+            cnt[(size_t)(idx[(size_t)p] / out.size) * (size_t)(nseg + 1) + (size_t)g]++;
+    out.ptr.assign((size_t)S * (size_t)(nseg + 1), 0);
+    int64_t run = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        for (int32_t g = 0; g <= nseg; ++g) {
+            out.ptr[(size_t)s * (nseg + 1) + g] = (int32_t)run;
+            if (g < nseg) run += cnt[(size_t)s * (nseg + 1) + g];
+        }
+    }
+    out.idx.resize((size_t)nnz);
+    out.src.resize((size_t)nnz);
+    std::vector<int32_t> pos(out.ptr);
+    for (int32_t g = 0; g < nseg; ++g)
+        for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
+            const int32_t s = idx[(size_t)p] / out.size;
+            const int32_t q = pos[(size_t)s * (nseg + 1) + g]++;
+            out.idx[(size_t)q] = idx[(size_t)p];
+            out.src[(size_t)q] = p;
+        }
+    out.tiles.clear();
+    std::vector<Tile> tt;
+    for (int32_t s = 0; s < S; ++s) {
+        const int32_t *sp = out.ptr.data() + (size_t)s * (nseg + 1);
+        build_tiles(sp, nseg, tile_nnz, tt);
+        for (Tile t : tt) { t.slice = s; out.tiles.push_back(t); }
+    }
+}
+
 void permute_and_transpose(const dpdlp_csr_lp *lp, int32_t block, uint64_t seed,
                            HostMatrix &H)
 {

@@ -12,8 +12,21 @@ namespace dpdlp {
 // Tile descriptor: 8 int32 (see dpdlp_build_tiles).
 struct Tile {
     int32_t seg_begin, seg_end, nnz_begin, nnz_end;
-    int32_t width_log2, piece, npieces, pad;
+    int32_t width_log2, piece, npieces, slice;   // slice: gather slice (sliced sets)
 };
+
+// A matrix format cut along its gathered dimension into S slices: slice s
+// holds the nonzeros whose index lies in [s*size, (s+1)*size), every segment
+// present in every slice (possibly empty).  ptr has S*(nseg+1) entries with
+// global nonzero offsets into idx; src[q] is the position in the unsliced
+// format the value of sliced nonzero q comes from; tiles carry their slice.
+struct SlicedHost {
+    int32_t S = 0, size = 0;
+    std::vector<int32_t> ptr, idx, src;
+    std::vector<Tile> tiles;
+};
+void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                  int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out);
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kTileNnzMax = 2048;    // products staged in LDS per tile

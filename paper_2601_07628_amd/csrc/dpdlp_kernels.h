@@ -112,8 +112,9 @@ constexpr int kPer = kTileNnzMax / kBlock;     // nonzeros per thread per tile
 constexpr int kPre = 2;                         // prefetched segments per thread
 
 template <class Op>
-__global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__ tiles,
-                                                 int ntiles,
+__global__ __launch_bounds__(kBlock) void k_tile(Op op0, const Tile *__restrict__ tiles,
+                                                 int ntiles, const int *__restrict__ blk2tile,
+                                                 int seg_stride,
                                                  const int *__restrict__ seg_ptr,
                                                  const int *__restrict__ idx,
                                                  const typename Op::MT *__restrict__ val,
@@ -131,9 +132,12 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__
     __shared__ double s_red[NQ][kBlock / 64];
     __shared__ AT s_redp[NR][kBlock / 64];
 
-    const int t = tile_of_block(remap);
-    if (t >= ntiles) return;
+    const int t = blk2tile ? blk2tile[blockIdx.x] : tile_of_block(remap);
+    if (t < 0 || t >= ntiles) return;
     const Tile d = tiles[t];
+    Op op = op0;
+    op.slice = d.slice;
+    seg_ptr += (size_t)d.slice * seg_stride;
     const int nnz0 = d.nnz_begin;
     const int cnt = d.nnz_end - d.nnz_begin;
     const int nseg = d.seg_end - d.seg_begin;
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op, const Tile *__restrict__
 
 // A segment split over npieces consecutive tiles starting at tile t0.
 struct SplitSeg {
-    int32_t seg, t0, npieces, pad;
+    int32_t seg, t0, npieces, slice;
 };
 
 // Finish split segments: one thread per split segment sums its pieces'
@@ -253,7 +257,7 @@ struct SplitSeg {
 // contribution goes to the slot of its first piece (the other pieces' slots
 // get zero), so every slot is written exactly once per pass.
 template <class Op>
-__global__ __launch_bounds__(64) void k_split_fix(Op op, const SplitSeg *__restrict__ splits,
+__global__ __launch_bounds__(64) void k_split_fix(Op op0, const SplitSeg *__restrict__ splits,
                                                    int nsplit, int ntiles,
                                                    const typename Op::AT *__restrict__ carries)
 {
@@ -264,6 +268,8 @@ __global__ __launch_bounds__(64) void k_split_fix(Op op, const SplitSeg *__restr
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsplit) return;
     const SplitSeg sg = splits[i];
+    Op op = op0;
+    op.slice = sg.slice;
     AT r[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
@@ -296,6 +302,7 @@ template <typename T>
 struct PrimalOp {
     using MT = T; using AT = T; using R = SumOp;
     static constexpr int NR = 1, NQ = 0;
+    int slice = 0;
     const T *__restrict__ y;
     const T *__restrict__ c;
     const T *__restrict__ lo;
@@ -336,6 +343,7 @@ template <typename T>
 struct DualOp {
     using MT = T; using AT = T; using R = SumOp;
     static constexpr int NR = 1, NQ = 0;
+    int slice = 0;
     const T *__restrict__ xbar;
     const T *__restrict__ lo;
     const T *__restrict__ hi;
@@ -365,6 +373,43 @@ struct DualOp {
     }
 };
 
+// Per-slice segment sums for the XCD-sliced form of the fused steps:
+//   partial[slice * nseg + seg] = sum over the slice's nonzeros of a * v[idx]
+template <typename T>
+struct PartialOp {
+    using MT = T; using AT = T; using R = SumOp;
+    static constexpr int NR = 1, NQ = 0;
+    int slice = 0;
+    const T *__restrict__ v;
+    T *__restrict__ partial;
+    double *partials;
+    int nseg;
+    using Pre = NoPre;
+    __device__ void value(MT a, int j, AT *o) const { o[0] = a * v[j]; }
+    __device__ void prefetch(int, Pre &) const {}
+    __device__ void epilogue(int s, const AT *r, const Pre &, double *) const
+    {
+        partial[(size_t)slice * nseg + s] = r[0];
+    }
+};
+
+// Adds the S slice partials of each segment in slice order and runs a fused
+// epilogue (PrimalOp / DualOp) on the sum; one thread per segment.
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_combine(Op op, int nseg, int S,
+                                                    const typename Op::AT *__restrict__ partial)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= nseg) return;
+    typename Op::Pre p;
+    op.prefetch(s, p);
+    typename Op::AT r[1];
+    r[0] = partial[s];
+    for (int q = 1; q < S; ++q) r[0] += partial[(size_t)q * nseg + s];
+    double acc[1];
+    op.epilogue(s, r, p, acc);
+}
+
 // ---------------------------------------------------------------------------
 // Check passes (App. B.4 KKT; App. B.2 / D.2.1 fixed-point residual; App. B.3
 // distances to the anchor), FP64 on the FP64 matrix.  TA: anchor type.
@@ -379,6 +424,7 @@ template <typename TA>
 struct CheckRowOp {
     using MT = double; using AT = double; using R = SumOp;
     static constexpr int NR = 2, NQ = 5;
+    int slice = 0;
     const double *__restrict__ xh;
     const double *__restrict__ dx;
     const double *__restrict__ yh;
@@ -421,6 +467,7 @@ template <typename TA>
 struct CheckColOp {
     using MT = double; using AT = double; using R = SumOp;
     static constexpr int NR = 1, NQ = 5;
+    int slice = 0;
     const double *__restrict__ yh;
     const double *__restrict__ xh;
     const double *__restrict__ dx;
@@ -457,6 +504,7 @@ struct CheckColOp {
 struct SpmvOp {
     using MT = double; using AT = double; using R = SumOp;
     static constexpr int NR = 1, NQ = 1;
+    int slice = 0;
     const double *__restrict__ in;
     const double *__restrict__ div;   // may be null
     double *__restrict__ out;
@@ -479,6 +527,7 @@ struct SpmvOp {
 struct AbsMaxOp {
     using MT = double; using AT = double; using R = MaxOp;
     static constexpr int NR = 1, NQ = 0;
+    int slice = 0;
     double *__restrict__ f;
     double *partials;
     __device__ void value(MT v, int, AT *o) const { o[0] = fabs(v); }
@@ -492,6 +541,7 @@ struct AbsMaxOp {
 struct AbsPowSumOp {
     using MT = double; using AT = double; using R = SumOp;
     static constexpr int NR = 1, NQ = 0;
+    int slice = 0;
     double *__restrict__ f;
     double *partials;
     double p;

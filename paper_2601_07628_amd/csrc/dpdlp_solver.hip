@@ -298,7 +298,28 @@ struct TileSet {
     int n = 0;
     SplitSeg *splits = nullptr;     // segments split over several tiles
     int nsplit = 0;
+    int *blk2tile = nullptr;        // sliced sets: workgroup -> tile (-1: idle)
+    int grid = 0;                   // sliced sets: launch size
+    int seg_stride = 0;             // sliced sets: nseg + 1
 };
+
+// One format cut into gather slices (the XCD-sliced form of a fused step).
+struct SlicedSet {
+    TileSet ts;
+    int S = 0;
+    int *ptr = nullptr, *idx = nullptr, *src = nullptr;
+    double *val = nullptr;
+    float *val32 = nullptr;
+};
+
+// Gathers the (scaled) values of the unsliced format into the sliced order.
+template <typename T>
+__global__ void k_gather_vals(const int *__restrict__ src, const double *__restrict__ val,
+                              T *__restrict__ out, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (T)val[src[i]];
+}
 
 struct DevMem {
     std::vector<void *> ptrs;
@@ -320,6 +341,8 @@ struct dpdlp_problem {
     double *v = nullptr, *vt = nullptr;
     float *v32 = nullptr, *vt32 = nullptr;
     TileSet tr, tc;
+    SlicedSet sr, sc;               // XCD-sliced CSR (dual) and CSC (primal)
+    void *part_slices = nullptr;    // S x max(m, n) per-slice segment sums
     void *carries = nullptr;
     double *part_r = nullptr, *part_c = nullptr;
     int *perm_row = nullptr, *perm_col = nullptr;
@@ -401,9 +424,9 @@ static void launch_tiles(dpdlp_problem *P, const Op &op, const TileSet &ts, cons
 {
     if (ts.n == 0) return;
     const int remap = P->prm.xcd_remap ? 1 : 0;
-    const int grid = remap ? ((ts.n + 7) / 8) * 8 : ts.n;
-    hipLaunchKernelGGL(k_tile<Op>, dim3(grid), dim3(kBlock), 0, P->s, op, ts.d, ts.n, seg_ptr,
-                       idx, val, (typename Op::AT *)P->carries, remap);
+    const int grid = ts.blk2tile ? ts.grid : (remap ? ((ts.n + 7) / 8) * 8 : ts.n);
+    hipLaunchKernelGGL(k_tile<Op>, dim3(grid), dim3(kBlock), 0, P->s, op, ts.d, ts.n, ts.blk2tile,
+                       ts.seg_stride, seg_ptr, idx, val, (typename Op::AT *)P->carries, remap);
     if (ts.nsplit)
         hipLaunchKernelGGL(k_split_fix<Op>, dim3((ts.nsplit + 63) / 64), dim3(64), 0, P->s, op,
                            ts.splits, ts.nsplit, ts.n, (const typename Op::AT *)P->carries);
@@ -469,6 +492,15 @@ static void launch_primal(dpdlp_problem *P, const T *y, const T *c, const T *lo,
     op.b = (T)(1.0 / (double)(k + 2));
     op.gamma = (T)P->prm.gamma;
     op.write_hat = write_hat;
+    if (P->sc.S > 0) {
+        PartialOp<T> po;
+        po.v = y; po.partial = (T *)P->part_slices; po.partials = nullptr; po.nseg = P->n;
+        launch_tiles(P, po, P->sc.ts, P->sc.ptr, P->sc.idx,
+                     (const T *)(sizeof(T) == 8 ? (const void *)P->sc.val : (const void *)P->sc.val32));
+        hipLaunchKernelGGL(k_combine<PrimalOp<T>>, dim3(nblk(P->n)), dim3(kBlock), 0, P->s, op, P->n,
+                           P->sc.S, (const T *)P->part_slices);
+        return;
+    }
     launch_tiles(P, op, P->tc, P->cp, P->ri, vt);
 }
 
@@ -484,6 +516,15 @@ static void launch_dual(dpdlp_problem *P, const T *xbar, const T *lo, const T *h
     op.b = (T)(1.0 / (double)(k + 2));
     op.gamma = (T)P->prm.gamma;
     op.write_hat = write_hat;
+    if (P->sr.S > 0) {
+        PartialOp<T> po;
+        po.v = xbar; po.partial = (T *)P->part_slices; po.partials = nullptr; po.nseg = P->m;
+        launch_tiles(P, po, P->sr.ts, P->sr.ptr, P->sr.idx,
+                     (const T *)(sizeof(T) == 8 ? (const void *)P->sr.val : (const void *)P->sr.val32));
+        hipLaunchKernelGGL(k_combine<DualOp<T>>, dim3(nblk(P->m)), dim3(kBlock), 0, P->s, op, P->m,
+                           P->sr.S, (const T *)P->part_slices);
+        return;
+    }
     launch_tiles(P, op, P->tr, P->rp, P->ci, v);
 }
 
@@ -560,7 +601,7 @@ static int build_tileset(dpdlp_problem *P, const std::vector<int32_t> &ptr, int3
     std::vector<SplitSeg> sp;
     for (int i = 0; i < ts.n; ++i) {
         const Tile &t = host_tiles[(size_t)i];
-        if (t.npieces > 0 && t.piece == 0) sp.push_back(SplitSeg{t.seg_begin, i, t.npieces, 0});
+        if (t.npieces > 0 && t.piece == 0) sp.push_back(SplitSeg{t.seg_begin, i, t.npieces, t.slice});
     }
     ts.nsplit = (int)sp.size();
     CHK(dalloc(P, &ts.d, host_tiles.size()));
@@ -570,6 +611,54 @@ static int build_tileset(dpdlp_problem *P, const std::vector<int32_t> &ptr, int3
         CHK(upload(P, ts.splits, sp.data(), sp.size() * sizeof(SplitSeg)));
     }
     HIPCHK(hipStreamSynchronize(P->s));     // host vectors are reused by the caller
+    return DPDLP_OK;
+}
+
+// Sliced copy of one format: tiles of slice s run on XCD s % 8 (workgroup b
+// runs on XCD b % 8), the slices of one XCD one after another.
+static int build_sliced(dpdlp_problem *P, const std::vector<int32_t> &ptr,
+                        const std::vector<int32_t> &idx, int32_t nseg, int32_t nidx, int S,
+                        SlicedSet &ss)
+{
+    SlicedHost sh;
+    slice_format(ptr, idx, nseg, nidx, S, P->prm.tile_nnz, sh);
+    ss.S = S;
+    const size_t nnz = sh.idx.size();
+    CHK(dalloc(P, &ss.ptr, sh.ptr.size()));
+    CHK(dalloc(P, &ss.idx, nnz));
+    CHK(dalloc(P, &ss.src, nnz));
+    CHK(dalloc(P, &ss.val, nnz));
+    CHK(upload(P, ss.ptr, sh.ptr.data(), sh.ptr.size() * sizeof(int32_t)));
+    if (nnz) {
+        CHK(upload(P, ss.idx, sh.idx.data(), nnz * sizeof(int32_t)));
+        CHK(upload(P, ss.src, sh.src.data(), nnz * sizeof(int32_t)));
+    }
+    TileSet &ts = ss.ts;
+    ts.n = (int)sh.tiles.size();
+    ts.seg_stride = nseg + 1;
+    std::vector<SplitSeg> sp;
+    std::vector<std::vector<int>> per(8);
+    for (int i = 0; i < ts.n; ++i) {
+        const Tile &tl = sh.tiles[(size_t)i];
+        if (tl.npieces > 0 && tl.piece == 0) sp.push_back(SplitSeg{tl.seg_begin, i, tl.npieces, tl.slice});
+        per[(size_t)(tl.slice % 8)].push_back(i);
+    }
+    size_t mx = 0;
+    for (auto &v : per) mx = std::max(mx, v.size());
+    std::vector<int> b2t(8 * mx, -1);
+    for (size_t x = 0; x < 8; ++x)
+        for (size_t q = 0; q < per[x].size(); ++q) b2t[8 * q + x] = per[x][q];
+    ts.grid = (int)b2t.size();
+    ts.nsplit = (int)sp.size();
+    CHK(dalloc(P, &ts.d, sh.tiles.size()));
+    CHK(upload(P, ts.d, sh.tiles.data(), sh.tiles.size() * sizeof(Tile)));
+    CHK(dalloc(P, &ts.blk2tile, b2t.size()));
+    CHK(upload(P, ts.blk2tile, b2t.data(), b2t.size() * sizeof(int)));
+    if (ts.nsplit) {
+        CHK(dalloc(P, &ts.splits, sp.size()));
+        CHK(upload(P, ts.splits, sp.data(), sp.size() * sizeof(SplitSeg)));
+    }
+    HIPCHK(hipStreamSynchronize(P->s));
     return DPDLP_OK;
 }
 
@@ -719,7 +808,18 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     std::vector<Tile> ht;
     CHK(build_tileset(P, H.rp, m, P->tr, ht));
     CHK(build_tileset(P, H.cp, n, P->tc, ht));
-    const int ntmax = std::max(P->tr.n, P->tc.n);
+    int ntmax = std::max(P->tr.n, P->tc.n);
+    const int S = P->prm.gather_slices;
+    if (S > 0) {
+        if (S % 8 != 0 || S > 64) {
+            set_error("gather_slices must be 0 or a multiple of 8 up to 64");
+            return DPDLP_E_INVALID_ARG;
+        }
+        CHK(build_sliced(P, H.rp, H.ci, m, n, S, P->sr));     // dual: gathers xbar
+        CHK(build_sliced(P, H.cp, H.ri, n, m, S, P->sc));     // primal: gathers y
+        ntmax = std::max(ntmax, std::max(P->sr.ts.n, P->sc.ts.n));
+        CHK(dalloc(P, (double **)&P->part_slices, (size_t)S * std::max(m, n)));
+    }
     CHK(dalloc(P, (double **)&P->carries, (size_t)2 * std::max(ntmax, 1)));
     CHK(dalloc(P, &P->part_r, (size_t)kNQ * std::max(P->tr.n, 1)));
     CHK(dalloc(P, &P->part_c, (size_t)kNQ * std::max(P->tc.n, 1)));
@@ -786,6 +886,12 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         apply_scale();
     }
     CHK(scale_data(P));
+    if (P->prm.gather_slices > 0) {
+        hipLaunchKernelGGL(k_gather_vals<double>, dim3(nblk((int64_t)nnz)), dim3(kBlock), 0, P->s,
+                           P->sr.src, P->v, P->sr.val, (int64_t)nnz);
+        hipLaunchKernelGGL(k_gather_vals<double>, dim3(nblk((int64_t)nnz)), dim3(kBlock), 0, P->s,
+                           P->sc.src, P->vt, P->sc.val, (int64_t)nnz);
+    }
     // A4: step size
     if (P->prm.eta > 0) {
         P->eta = P->prm.eta;
@@ -806,6 +912,10 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
             if (k) hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(k)), dim3(kBlock), 0, P->s, a, b, k);
         };
         cv(P->v, P->v32, (int64_t)nnz); cv(P->vt, P->vt32, (int64_t)nnz);
+        if (P->prm.gather_slices > 0) {
+            CHK(dalloc(P, &P->sr.val32, nnz)); CHK(dalloc(P, &P->sc.val32, nnz));
+            cv(P->sr.val, P->sr.val32, (int64_t)nnz); cv(P->sc.val, P->sc.val32, (int64_t)nnz);
+        }
         CHK(scale_data(P));
     }
     HIPCHK(hipGetLastError());

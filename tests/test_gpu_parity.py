@@ -165,6 +165,28 @@ def test_iterate_parity(D, O, name, maker, n_iters):
     fixed_run(D, O, maker(), n_iters)
 
 
+@pytest.mark.parametrize("name,maker,n_iters", [
+    ("c0", lpgen.config0, 500),
+    ("huge-share-small", lambda: lpgen.huge_share_lp(m=20000, n=40000, seed=9), 300),
+    ("transport-60x4000", lambda: lpgen.transport_lp(60, 4000, seed=3), 300),
+])
+@pytest.mark.parametrize("slices", [8, 16])
+def test_iterate_parity_xcd_sliced(D, O, name, maker, n_iters, slices):
+    """The XCD-sliced fused steps (per-slice partial sums added in slice
+    order) change only the summation order."""
+    fixed_run(D, O, maker(), n_iters, gpu_kw=dict(gather_slices=slices))
+
+
+def test_sliced_fp32_mixed_and_determinism(D, O):
+    lp = lpgen.config4()
+    r1 = D.Problem(lp, gpu_params(D, precision=D.FP32_MIXED, gather_slices=8)).solve()
+    r2 = D.Problem(lp, gpu_params(D, precision=D.FP32_MIXED, gather_slices=8)).solve()
+    assert r1["status"] == 1 and max(r1["r_primal"], r1["r_dual"], r1["r_gap"]) <= 1e-8
+    assert np.array_equal(r1["x"], r2["x"]) and np.array_equal(r1["y"], r2["y"])
+    o = O.Problem(lp).solve()
+    assert abs(r1["obj_primal"] - o["obj_p"]) <= 1e-7 * (1 + abs(o["obj_p"]))
+
+
 @pytest.mark.parametrize("remap,block", [(0, 256), (1, 0)])
 def test_iterate_parity_launch_variants(D, O, remap, block):
     """XCD remap off / permutation off change only the summation order."""
@@ -194,6 +216,7 @@ def test_split_segments_long_row_and_column(D, O):
                   rng.standard_normal(n), lo, hi, -np.ones(n), np.ones(n), name="split")
     fixed_run(D, O, lp, 300)
     fixed_run(D, O, lp, 300, gpu_kw=dict(tile_nnz=512))
+    fixed_run(D, O, lp, 300, gpu_kw=dict(tile_nnz=512, gather_slices=8))
 
 
 def test_edge_cases_empty_rows_cols_free_rows(D, O):
