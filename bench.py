@@ -119,7 +119,7 @@ def time_to_tol(D, lp, torch, **kw):
     return out
 
 
-def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3):
+def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3, eps_list=(1e-6, 1e-8)):
     """Config-4 family: targets from the FP64 solver, network trained on the
     GPU, held-out members solved cold / from the mean solution / from the
     network (with the KKT-judged fallback) to 1e-6 and 1e-8."""
@@ -127,8 +127,10 @@ def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3):
     import lpgen
     from paper_2601_07628_amd import warmstart as W
     base = lpgen.config4()
-    insts = [lpgen.config4_family(i, base) for i in range(n_train + n_test)]
-    train_i, test_i = insts[:n_train], insts[n_train:]
+    # members 0..383 train and 384..511 are held out in the full protocol;
+    # the compact one takes the first n_train and the first n_test of each
+    train_i = [lpgen.config4_family(i, base) for i in range(n_train)]
+    test_i = [lpgen.config4_family(384 + i, base) for i in range(n_test)]
     G = D.Problem(base, gpu_params(D, eps=1e-8, max_iters=200000),
                   stream=torch.cuda.current_stream())
     t0 = time.perf_counter()
@@ -146,7 +148,7 @@ def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3):
     out = {"train_instances": n_train, "targets_converged": ok, "held_out": n_test,
            "targets_seconds": round(t_targets, 2), "train_seconds": round(t_train, 2),
            "epochs": epochs, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
-    for eps in (1e-6, 1e-8):
+    for eps in eps_list:
         G.set_params(eps=eps)
         row = {}
         for mode in ("cold", "mean", "gnn"):
@@ -155,7 +157,9 @@ def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3):
             row[mode] = {"mean_iters": round(float(np.mean([r["iters"] for r in rs])), 1),
                          "mean_ms": round(1e3 * float(np.mean([r["seconds"] for r in rs])), 3),
                          "converged": len(conv),
-                         "fallbacks": int(sum(r["fallback"] for r in rs))}
+                         "fallbacks": int(sum(r["fallback"] for r in rs)),
+                         "choices": {c: sum(r["choice"] == c for r in rs)
+                                     for c in ("both", "primal", "dual", "cold")}}
         out[f"eps_{eps:g}"] = row
         log(f"warm start eps={eps:g}: {row}")
     net.close()
@@ -173,6 +177,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--ws-train", type=int, default=16,
+                    help="warm-start family members used for training (full protocol: 384)")
+    ap.add_argument("--ws-test", type=int, default=4,
+                    help="held-out members (full protocol: 128)")
+    ap.add_argument("--ws-epochs", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 256 MiB buffer (device to device), a kernel of "
                          "known size that calibrates the HBM byte counters")
@@ -239,32 +248,45 @@ def main():
     step_bytes = prof["primal"]["bytes_per_launch"] + prof["dual"]["bytes_per_launch"]
 
     extra = {}
-    if not args.no_extra:
+
+    def guarded(name, fn):
+        """Run an optional measurement; a failure is recorded, not fatal."""
+        try:
+            fn()
+        except Exception as e:            # noqa: BLE001 - reported in the JSON line
+            extra[f"{name}_error"] = f"{type(e).__name__}: {e}"
+            log(f"{name} failed: {e}")
+
+    def spmv():
         ms_r, b_r = G.time_kernel(2, 20)
         ms_c, b_c = G.time_kernel(3, 20)
         extra["spmv_GBps"] = {"csr_Ax": round(b_r / ms_r / 1e6, 1),
                               "csc_ATy": round(b_c / ms_c / 1e6, 1),
                               "csr_ms": round(ms_r, 4), "csc_ms": round(ms_c, 4)}
         log(f"SpMV: {extra['spmv_GBps']}")
+
+    if not args.no_extra:
+        guarded("spmv", spmv)
     G.close()
     del G
 
-    if not args.no_extra:
-        for S in (8, 16):
-            GS = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9, gather_slices=S),
-                           stream=stream)
-            GS.init()
-            GS.iterate(ips)
-            GS.profile_enable(True)
-            elS = timed_steps(GS, max(5, args.steps // 2), ips, torch)
-            pS = GS.profile()
-            extra[f"fp64_xcd_sliced_{S}"] = {
-                "iters_per_s": round(max(5, args.steps // 2) * ips / elS, 1),
-                "primal_ms": round(pS["primal"]["total_ms"] / max(pS["primal"]["launches"], 1), 4),
-                "dual_ms": round(pS["dual"]["total_ms"] / max(pS["dual"]["launches"], 1), 4)}
-            log(f"FP64 XCD-sliced S={S}: {extra[f'fp64_xcd_sliced_{S}']}")
-            GS.close()
-            del GS
+    def sliced(S):
+        GS = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9, gather_slices=S),
+                       stream=stream)
+        GS.init()
+        GS.iterate(ips)
+        GS.profile_enable(True)
+        nst = max(5, args.steps // 2)
+        elS = timed_steps(GS, nst, ips, torch)
+        pS = GS.profile()
+        extra[f"fp64_xcd_sliced_{S}"] = {
+            "iters_per_s": round(nst * ips / elS, 1),
+            "primal_ms": round(pS["primal"]["total_ms"] / max(pS["primal"]["launches"], 1), 4),
+            "dual_ms": round(pS["dual"]["total_ms"] / max(pS["dual"]["launches"], 1), 4)}
+        log(f"FP64 XCD-sliced S={S}: {extra[f'fp64_xcd_sliced_{S}']}")
+        GS.close()
+
+    def fp32():
         G32 = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9,
                                         precision=D.FP32_MIXED, fp32_stall_checks=10**6,
                                         fp32_switch_tol=0.0), stream=stream)
@@ -277,16 +299,28 @@ def main():
                                   "in_fp32": int(r32["fp32_iters"]) == int(r32["iters"])}
         log(f"FP32-mixed: {extra['fp32_mixed_c1']}")
         G32.close()
-        del G32
-        for name, mk in (("c0", lpgen.config0), ("c4", lpgen.config4)):
-            inst = mk()
-            extra[f"time_to_tol_{name}"] = {
-                "fp64": time_to_tol(D, inst, torch),
-                "fp32_mixed": time_to_tol(D, inst, torch, precision=D.FP32_MIXED)}
-            log(f"time-to-tolerance {name}: {extra[f'time_to_tol_{name}']}")
 
-    if not args.no_extra and not args.no_warmstart:
-        extra["warm_start_c4"] = warmstart_eval(D, torch)
+    def ttt(name, mk):
+        inst = mk()
+        extra[f"time_to_tol_{name}"] = {
+            "fp64": time_to_tol(D, inst, torch),
+            "fp32_mixed": time_to_tol(D, inst, torch, precision=D.FP32_MIXED)}
+        log(f"time-to-tolerance {name}: {extra[f'time_to_tol_{name}']}")
+
+    def ws():
+        full = args.ws_train >= 384
+        extra["warm_start_c4"] = warmstart_eval(
+            D, torch, n_train=args.ws_train, n_test=args.ws_test, epochs=args.ws_epochs,
+            eps_list=(1e-6, 1e-8) if full else (1e-8,))
+
+    if not args.no_extra:
+        for S in (8, 16):
+            guarded(f"fp64_xcd_sliced_{S}", lambda S=S: sliced(S))
+        guarded("fp32_mixed_c1", fp32)
+        for name, mk in (("c0", lpgen.config0), ("c4", lpgen.config4)):
+            guarded(f"time_to_tol_{name}", lambda name=name, mk=mk: ttt(name, mk))
+        if not args.no_warmstart:
+            guarded("warm_start_c4", ws)
 
     cpu = None
     if not args.no_cpu:

@@ -88,7 +88,9 @@ typedef struct dpdlp_params {
     int32_t perm_block;       /* 256: block size of the block-wise random    */
                               /* permutation (Sec. 4.2); 0: no permutation   */
     int32_t tile_nnz;         /* nonzeros per workgroup tile (Sec. 4.3 at CU */
-                              /* granularity); 0 = default 2048, max 2048    */
+                              /* granularity), max 2048; 0 = automatic: the  */
+                              /* power of two in [256, 2048] nearest above   */
+                              /* nnz / 2048 (about 8 tiles per CU)           */
     uint64_t perm_seed;       /* seed of the block permutation               */
     int32_t precision;        /* DPDLP_FP64 or DPDLP_FP32_MIXED              */
     int32_t xcd_remap;        /* 1: map consecutive tiles onto one XCD        */
@@ -99,6 +101,10 @@ typedef struct dpdlp_params {
                               /* slices, slice s on XCD s % 8, partial sums   */
                               /* added per segment in slice order (the 2-D    */
                               /* partition of Sec. 3.1 across the 8 XCDs)     */
+    int32_t use_graphs;       /* 1: replay the check_period - 1 iterations    */
+                              /* between two checks as one HIP graph (off    */
+                              /* while dpdlp_profile_enable is on)           */
+    int32_t pad1;
 } dpdlp_params;
 
 typedef struct dpdlp_result {
@@ -156,8 +162,8 @@ int dpdlp_problem_update_data(dpdlp_problem *prob, const double *c, const double
                               const double *var_hi, int32_t mem_kind, void *stream);
 
 /* Change the run-time parameters of a prepared problem: eps, max_iters,
- * time_limit, check_period, gamma, beta_*, kp/ki/kd, xcd_remap and the FP32
- * switch rule.  The other fields (scaling, step size, permutation, tiles,
+ * time_limit, check_period, gamma, beta_*, kp/ki/kd, xcd_remap, use_graphs
+ * and the FP32 switch rule.  The other fields (scaling, step size, permutation, tiles,
  * precision) are fixed at creation and ignored here.  Errors: INVALID_ARG. */
 int dpdlp_set_params(dpdlp_problem *prob, const dpdlp_params *params);
 

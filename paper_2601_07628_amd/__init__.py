@@ -54,10 +54,11 @@ class Params(C.Structure):
                 ("tile_nnz", C.c_int32), ("perm_seed", C.c_uint64),
                 ("precision", C.c_int32), ("xcd_remap", C.c_int32),
                 ("fp32_switch_tol", C.c_double), ("fp32_stall_checks", C.c_int32),
-                ("gather_slices", C.c_int32)]
+                ("gather_slices", C.c_int32), ("use_graphs", C.c_int32),
+                ("pad1", C.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad1"}
 
 
 class Result(C.Structure):

@@ -125,14 +125,15 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16 *__restrict__ A, long a
             }
 }
 
-// out[e] = sum_z part[z * stride + e], z in chunk order.
-__global__ void k_sum_chunks(const float *__restrict__ part, long stride, int nz, float *out, long n)
+// out[e] (+)= sum_z part[z * stride + e], z in chunk order.
+__global__ void k_sum_chunks(const float *__restrict__ part, long stride, int nz, float *out, long n,
+                             int accum)
 {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     float s = 0.f;
     for (int z = 0; z < nz; ++z) s += part[(long)z * stride + e];
-    out[e] = s;
+    out[e] = accum ? out[e] + s : s;
 }
 
 // out[s, :] (+)= sum_{p in segment s} a_p in[idx_p, :]; one wave per segment,
@@ -285,15 +286,20 @@ __global__ __launch_bounds__(kH) void k_head_wgrad(int n, int chunk, const bf16 
     part[(long)c * kH + f] = s;
 }
 
-// dZ = dH * [H > 0] as BF16 (the ReLU derivative on the stored output)
+// dZ = dH * [H > 0] (the ReLU derivative on the stored output), as a BF16
+// pair hi + lo with hi = bf16(dZ), lo = bf16(dZ - hi): the gradient GEMMs run
+// both on the matrix cores and add them in FP32 (about 16 mantissa bits).
 __global__ void k_relu_bwd(long rows, const float *__restrict__ dH, long dld,
-                           const bf16 *__restrict__ Hout, long hld, bf16 *__restrict__ dZ)
+                           const bf16 *__restrict__ Hout, long hld, bf16 *__restrict__ dZ,
+                           bf16 *__restrict__ dZlo)
 {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= rows * kH) return;
     const long r = e / kH, f = e % kH;
     const float g = bf2f(Hout[r * hld + f]) > 0.f ? dH[r * dld + f] : 0.f;
-    dZ[r * kH + f] = f2bf(g);
+    const bf16 hi = f2bf(g);
+    dZ[r * kH + f] = hi;
+    dZlo[r * kH + f] = f2bf(g - bf2f(hi));
 }
 
 // dst[r, 0:128] = src[r, 0:128] (strided f32 copy)
@@ -380,7 +386,7 @@ struct dpdlp_gnn {
     std::vector<bf16 *> INc, INr;          // index 1..L
     bf16 *Hc_last = nullptr, *Hr_last = nullptr;
     float *dHc = nullptr, *dHr = nullptr, *dINc = nullptr, *dINr = nullptr;
-    bf16 *dZc = nullptr, *dZr = nullptr;
+    bf16 *dZc = nullptr, *dZr = nullptr, *dZc_lo = nullptr, *dZr_lo = nullptr;
     float *wpart = nullptr;
     double *lpart = nullptr, *lsum = nullptr;
     double *ref_c = nullptr, *ref_b = nullptr, *ref_x = nullptr, *ref_y = nullptr;
@@ -427,14 +433,29 @@ void gemm(dpdlp_gnn *G, const bf16 *A, long a_rs, long a_cs, const bf16 *B, long
                        b_rs, b_cs, C, ldc, 0L, M, Nc, K, K, flags);
 }
 
-// weight gradient  out[M x Nc] = A^T[M x K] dZ[K x Nc]  (split K, chunk order)
-void wgrad(dpdlp_gnn *G, const bf16 *A, long a_ld, int M, const bf16 *dZ, int K, float *out)
+// weight gradient  out[M x Nc] (+)= A^T[M x K] dZ[K x Nc]  (split K, chunk order)
+void wgrad1(dpdlp_gnn *G, const bf16 *A, long a_ld, int M, const bf16 *dZ, int K, float *out,
+            int accum)
 {
     const int nz = (K + kKC - 1) / kKC;
     const long zs = (long)M * kH;
     hipLaunchKernelGGL(k_gemm, dim3(nb(M, 64), nb(kH, 64), nz), dim3(256), 0, G->s, A, 1L, a_ld, dZ,
                        (long)kH, 1L, (void *)G->wpart, (long)kH, zs, M, kH, K, kKC, 0);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nb(zs)), dim3(256), 0, G->s, G->wpart, zs, nz, out, zs);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nb(zs)), dim3(256), 0, G->s, G->wpart, zs, nz, out, zs,
+                       accum);
+}
+// with dZ given as the BF16 pair (hi, lo)
+void wgrad(dpdlp_gnn *G, const bf16 *A, long a_ld, int M, const bf16 *dZ, const bf16 *dZlo, int K,
+           float *out)
+{
+    wgrad1(G, A, a_ld, M, dZ, K, out, 0);
+    wgrad1(G, A, a_ld, M, dZlo, K, out, 1);
+}
+// data gradient  out[N x 256] = dZ W^T with dZ = hi + lo (FP32 output)
+void dgrad(dpdlp_gnn *G, const bf16 *dZ, const bf16 *dZlo, const bf16 *W, float *out, int N)
+{
+    gemm(G, dZ, kH, 1, W, 1, kH, out, 2 * kH, N, 2 * kH, kH, 0);
+    gemm(G, dZlo, kH, 1, W, 1, kH, out, 2 * kH, N, 2 * kH, kH, G_ACCUM);
 }
 
 template <typename TI, typename TO>
@@ -494,9 +515,9 @@ void backward(dpdlp_gnn *G)
     const int ch = 1024;
     const int ncx = (n + ch - 1) / ch, ncy = (m + ch - 1) / ch;
     hipLaunchKernelGGL(k_head_wgrad, dim3(ncx), dim3(kH), 0, G->s, n, ch, G->Hc_last, (long)kH, G->dpx, G->wpart);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kH), 0, G->s, G->wpart, (long)kH, ncx, G->g + G->off_wx, (long)kH);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kH), 0, G->s, G->wpart, (long)kH, ncx, G->g + G->off_wx, (long)kH, 0);
     hipLaunchKernelGGL(k_head_wgrad, dim3(ncy), dim3(kH), 0, G->s, m, ch, G->Hr_last, (long)kH, G->dpy, G->wpart);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kH), 0, G->s, G->wpart, (long)kH, ncy, G->g + G->off_wy, (long)kH);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(kH), 0, G->s, G->wpart, (long)kH, ncy, G->g + G->off_wy, (long)kH, 0);
 
     for (int l = L; l >= 1; --l) {
         long ldc, ldr;
@@ -504,15 +525,15 @@ void backward(dpdlp_gnn *G)
         const bf16 *Hr = Hr_of(G, l, &ldr);
         // column update of layer l
         hipLaunchKernelGGL(k_relu_bwd, dim3(nb((long)n * kH)), dim3(256), 0, G->s, (long)n, G->dHc,
-                           (long)kH, Hc, ldc, G->dZc);
-        wgrad(G, G->INc[l], 2 * kH, 2 * kH, G->dZc, n, G->g + G->off_c[(size_t)l - 1]);
-        gemm(G, G->dZc, kH, 1, G->wb + G->off_c[(size_t)l - 1], 1, kH, G->dINc, 2 * kH, n, 2 * kH, kH, 0);
+                           (long)kH, Hc, ldc, G->dZc, G->dZc_lo);
+        wgrad(G, G->INc[l], 2 * kH, 2 * kH, G->dZc, G->dZc_lo, n, G->g + G->off_c[(size_t)l - 1]);
+        dgrad(G, G->dZc, G->dZc_lo, G->wb + G->off_c[(size_t)l - 1], G->dINc, n);
         spmm<float, float>(G, true, G->dINc + kH, 2 * kH, G->dHr, kH, 1);   // dH_r^l += A~ dS_c
         // row update of layer l
         hipLaunchKernelGGL(k_relu_bwd, dim3(nb((long)m * kH)), dim3(256), 0, G->s, (long)m, G->dHr,
-                           (long)kH, Hr, ldr, G->dZr);
-        wgrad(G, G->INr[l], 2 * kH, 2 * kH, G->dZr, m, G->g + G->off_r[(size_t)l - 1]);
-        gemm(G, G->dZr, kH, 1, G->wb + G->off_r[(size_t)l - 1], 1, kH, G->dINr, 2 * kH, m, 2 * kH, kH, 0);
+                           (long)kH, Hr, ldr, G->dZr, G->dZr_lo);
+        wgrad(G, G->INr[l], 2 * kH, 2 * kH, G->dZr, G->dZr_lo, m, G->g + G->off_r[(size_t)l - 1]);
+        dgrad(G, G->dZr, G->dZr_lo, G->wb + G->off_r[(size_t)l - 1], G->dINr, m);
         // gradients of the previous layer's outputs
         hipLaunchKernelGGL(k_copy_rows, dim3(nb((long)n * kH)), dim3(256), 0, G->s, (long)n, G->dINc,
                            2L * kH, G->dHc, (long)kH);
@@ -522,11 +543,11 @@ void backward(dpdlp_gnn *G)
     }
     // embeddings
     hipLaunchKernelGGL(k_relu_bwd, dim3(nb((long)n * kH)), dim3(256), 0, G->s, (long)n, G->dHc,
-                       (long)kH, G->INc[1], 2L * kH, G->dZc);
-    wgrad(G, G->Xc, kF, kF, G->dZc, n, G->g + G->off_cin);
+                       (long)kH, G->INc[1], 2L * kH, G->dZc, G->dZc_lo);
+    wgrad(G, G->Xc, kF, kF, G->dZc, G->dZc_lo, n, G->g + G->off_cin);
     hipLaunchKernelGGL(k_relu_bwd, dim3(nb((long)m * kH)), dim3(256), 0, G->s, (long)m, G->dHr,
-                       (long)kH, G->INr[1], 2L * kH, G->dZr);
-    wgrad(G, G->Xr, kF, kF, G->dZr, m, G->g + G->off_rin);
+                       (long)kH, G->INr[1], 2L * kH, G->dZr, G->dZr_lo);
+    wgrad(G, G->Xr, kF, kF, G->dZr, G->dZr_lo, m, G->g + G->off_rin);
 }
 
 // host or device double vector -> device (staging through tmp when host)
@@ -605,6 +626,8 @@ int dpdlp_gnn_create(dpdlp_problem *prob, int32_t layers, void *stream, dpdlp_gn
     RCHK(galloc(G.get(), &G->dINr, (size_t)m * 2 * kH));
     RCHK(galloc(G.get(), &G->dZc, (size_t)n * kH));
     RCHK(galloc(G.get(), &G->dZr, (size_t)m * kH));
+    RCHK(galloc(G.get(), &G->dZc_lo, (size_t)n * kH));
+    RCHK(galloc(G.get(), &G->dZr_lo, (size_t)m * kH));
     const long nzmax = (std::max(n, m) + kKC - 1) / kKC;
     RCHK(galloc(G.get(), &G->wpart, (size_t)std::max<long>(nzmax * 2 * kH * kH, (n / 1024 + 2) * kH)));
     RCHK(galloc(G.get(), &G->lpart, (size_t)(nb(n) + nb(m))));

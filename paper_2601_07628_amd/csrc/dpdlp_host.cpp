@@ -325,6 +325,8 @@ void dpdlp_params_default(dpdlp_params *p)
     p->xcd_remap = 1;
     p->fp32_switch_tol = 1e-6;
     p->fp32_stall_checks = 8;
+    p->gather_slices = 0;
+    p->use_graphs = 1;
 }
 
 const char *dpdlp_status_string(int32_t s)

@@ -137,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op0, const Tile *__restrict_
     const Tile d = tiles[t];
     Op op = op0;
     op.slice = d.slice;
+    op.resolve();
     seg_ptr += (size_t)d.slice * seg_stride;
     const int nnz0 = d.nnz_begin;
     const int cnt = d.nnz_end - d.nnz_begin;
@@ -270,6 +271,7 @@ __global__ __launch_bounds__(64) void k_split_fix(Op op0, const SplitSeg *__rest
     const SplitSeg sg = splits[i];
     Op op = op0;
     op.slice = sg.slice;
+    op.resolve();
     AT r[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
@@ -291,6 +293,14 @@ __global__ __launch_bounds__(64) void k_split_fix(Op op0, const SplitSeg *__rest
 
 struct NoPre {};
 
+// Iteration scalars read from device memory by graph-replayed launches:
+// the primal / dual step size and the Halpern index of the run's first
+// iteration (the launch adds its offset j inside the run).
+struct IterDev {
+    double tau, sigma;
+    long long k0;
+};
+
 // ---------------------------------------------------------------------------
 // Fused PDHG steps (Sec. 2.2 / Algorithm 1 steps 1-2, with the reflected
 // Halpern update of App. A fused in).  T is double (FP64) or float (FP32).
@@ -303,6 +313,14 @@ struct PrimalOp {
     using MT = T; using AT = T; using R = SumOp;
     static constexpr int NR = 1, NQ = 0;
     int slice = 0;
+    __device__ void resolve()
+    {
+        if (!dev) return;
+        const double kk = (double)(dev->k0 + j);
+        tau = (T)dev->tau;
+        a = (T)((kk + 1.0) / (kk + 2.0));
+        b = (T)(1.0 / (kk + 2.0));
+    }
     const T *__restrict__ y;
     const T *__restrict__ c;
     const T *__restrict__ lo;
@@ -315,6 +333,8 @@ struct PrimalOp {
     double *partials;
     T tau, a, b, gamma;
     int write_hat;
+    const IterDev *dev = nullptr;   // graph replays: tau and k from here
+    int j = 0;
     struct Pre { T x, c, lo, hi, xa; };
     __device__ void value(MT v, int j, AT *out) const { out[0] = v * y[j]; }
     __device__ void prefetch(int j, Pre &p) const
@@ -344,6 +364,14 @@ struct DualOp {
     using MT = T; using AT = T; using R = SumOp;
     static constexpr int NR = 1, NQ = 0;
     int slice = 0;
+    __device__ void resolve()
+    {
+        if (!dev) return;
+        const double kk = (double)(dev->k0 + j);
+        sigma = (T)dev->sigma;
+        a = (T)((kk + 1.0) / (kk + 2.0));
+        b = (T)(1.0 / (kk + 2.0));
+    }
     const T *__restrict__ xbar;
     const T *__restrict__ lo;
     const T *__restrict__ hi;
@@ -354,6 +382,8 @@ struct DualOp {
     double *partials;
     T sigma, a, b, gamma;
     int write_hat;
+    const IterDev *dev = nullptr;
+    int j = 0;
     struct Pre { T y, lo, hi, ya; };
     __device__ void value(MT v, int j, AT *out) const { out[0] = v * xbar[j]; }
     __device__ void prefetch(int i, Pre &p) const
@@ -380,6 +410,7 @@ struct PartialOp {
     using MT = T; using AT = T; using R = SumOp;
     static constexpr int NR = 1, NQ = 0;
     int slice = 0;
+    __device__ void resolve() {}
     const T *__restrict__ v;
     T *__restrict__ partial;
     double *partials;
@@ -396,11 +427,13 @@ struct PartialOp {
 // Adds the S slice partials of each segment in slice order and runs a fused
 // epilogue (PrimalOp / DualOp) on the sum; one thread per segment.
 template <class Op>
-__global__ __launch_bounds__(kBlock) void k_combine(Op op, int nseg, int S,
+__global__ __launch_bounds__(kBlock) void k_combine(Op op0, int nseg, int S,
                                                     const typename Op::AT *__restrict__ partial)
 {
     const int s = blockIdx.x * kBlock + threadIdx.x;
     if (s >= nseg) return;
+    Op op = op0;
+    op.resolve();
     typename Op::Pre p;
     op.prefetch(s, p);
     typename Op::AT r[1];
@@ -425,6 +458,7 @@ struct CheckRowOp {
     using MT = double; using AT = double; using R = SumOp;
     static constexpr int NR = 2, NQ = 5;
     int slice = 0;
+    __device__ void resolve() {}
     const double *__restrict__ xh;
     const double *__restrict__ dx;
     const double *__restrict__ yh;
@@ -468,6 +502,7 @@ struct CheckColOp {
     using MT = double; using AT = double; using R = SumOp;
     static constexpr int NR = 1, NQ = 5;
     int slice = 0;
+    __device__ void resolve() {}
     const double *__restrict__ yh;
     const double *__restrict__ xh;
     const double *__restrict__ dx;
@@ -505,6 +540,7 @@ struct SpmvOp {
     using MT = double; using AT = double; using R = SumOp;
     static constexpr int NR = 1, NQ = 1;
     int slice = 0;
+    __device__ void resolve() {}
     const double *__restrict__ in;
     const double *__restrict__ div;   // may be null
     double *__restrict__ out;
@@ -528,6 +564,7 @@ struct AbsMaxOp {
     using MT = double; using AT = double; using R = MaxOp;
     static constexpr int NR = 1, NQ = 0;
     int slice = 0;
+    __device__ void resolve() {}
     double *__restrict__ f;
     double *partials;
     __device__ void value(MT v, int, AT *o) const { o[0] = fabs(v); }
@@ -542,6 +579,7 @@ struct AbsPowSumOp {
     using MT = double; using AT = double; using R = SumOp;
     static constexpr int NR = 1, NQ = 0;
     int slice = 0;
+    __device__ void resolve() {}
     double *__restrict__ f;
     double *partials;
     double p;

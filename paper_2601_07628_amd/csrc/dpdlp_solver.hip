@@ -377,6 +377,10 @@ struct dpdlp_problem {
     bool initialized = false;
     double setup_seconds = 0, solve_seconds = 0;
     std::vector<dpdlp_log_rec> log;
+    // graph replay of the runs between checks
+    IterDev *iterdev = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipStream_t gstream = nullptr;
     // profiling
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[8];
@@ -482,9 +486,11 @@ static void prof_collect(dpdlp_problem *P)
 template <typename T>
 static void launch_primal(dpdlp_problem *P, const T *y, const T *c, const T *lo, const T *hi,
                           const T *xa, T *x, T *xbar, const T *vt, double tau, int64_t k,
-                          int write_hat)
+                          int write_hat, const IterDev *dev = nullptr, int j = 0)
 {
     PrimalOp<T> op;
+    op.dev = dev;
+    op.j = j;
     op.y = y; op.c = c; op.lo = lo; op.hi = hi; op.xa = xa; op.x = x; op.xbar = xbar;
     op.xh = P->xh; op.dx = P->dx; op.partials = nullptr;
     op.tau = (T)tau;
@@ -506,9 +512,12 @@ static void launch_primal(dpdlp_problem *P, const T *y, const T *c, const T *lo,
 
 template <typename T>
 static void launch_dual(dpdlp_problem *P, const T *xbar, const T *lo, const T *hi, const T *ya,
-                        T *y, const T *v, double sigma, int64_t k, int write_hat)
+                        T *y, const T *v, double sigma, int64_t k, int write_hat,
+                        const IterDev *dev = nullptr, int j = 0)
 {
     DualOp<T> op;
+    op.dev = dev;
+    op.j = j;
     op.xbar = xbar; op.lo = lo; op.hi = hi; op.ya = ya; op.y = y;
     op.yh = P->yh; op.dy = P->dy; op.partials = nullptr;
     op.sigma = (T)sigma;
@@ -528,24 +537,65 @@ static void launch_dual(dpdlp_problem *P, const T *xbar, const T *lo, const T *h
     launch_tiles(P, op, P->tr, P->rp, P->ci, v);
 }
 
-// One PDHG + Halpern iteration in the current precision.
-static void pdhg_iteration(dpdlp_problem *P, double tau, double sigma, int64_t k, int write_hat)
+// One PDHG + Halpern iteration in the current precision.  With dev set, the
+// step sizes and the Halpern index (k0 + j) are read from device memory (graph
+// replays); the arguments tau, sigma, k are then unused.
+static void pdhg_iteration(dpdlp_problem *P, double tau, double sigma, int64_t k, int write_hat,
+                           const IterDev *dev = nullptr, int j = 0)
 {
     if (P->in_fp32) {
         { ProfScope ps(P, 0);
           launch_primal<float>(P, P->y32, P->c32, P->vlo32, P->vhi32, P->xa32, P->x32, P->xbar32,
-                               P->vt32, tau, k, write_hat); }
+                               P->vt32, tau, k, write_hat, dev, j); }
         { ProfScope ps(P, 1);
           launch_dual<float>(P, P->xbar32, P->clo32, P->chi32, P->ya32, P->y32, P->v32, sigma, k,
-                             write_hat); }
+                             write_hat, dev, j); }
     } else {
         { ProfScope ps(P, 0);
           launch_primal<double>(P, P->y, P->c, P->vlo, P->vhi, P->xa, P->x, P->xbar, P->vt, tau,
-                                k, write_hat); }
+                                k, write_hat, dev, j); }
         { ProfScope ps(P, 1);
           launch_dual<double>(P, P->xbar, P->clo, P->chi, P->ya, P->y, P->v, sigma, k,
-                              write_hat); }
+                              write_hat, dev, j); }
     }
+}
+
+__global__ void k_set_iter(IterDev *d, double tau, double sigma, long long k0)
+{
+    d->tau = tau;
+    d->sigma = sigma;
+    d->k0 = k0;
+}
+
+// The check_period - 1 iterations between two checks as one HIP graph (one
+// per precision), captured on a private stream on first use and replayed on
+// the solver's stream after k_set_iter has written the run's scalars.
+static int run_graph(dpdlp_problem *P, double tau, double sigma, int64_t k0, int L)
+{
+    hipGraphExec_t &ge = P->graph[P->in_fp32 ? 1 : 0];
+    if (!ge) {
+        if (!P->gstream) HIPCHK(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
+        hipStream_t saved = P->s;
+        P->s = P->gstream;
+        HIPCHK(hipStreamBeginCapture(P->gstream, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < L; ++j) pdhg_iteration(P, 0.0, 0.0, 0, 0, P->iterdev, j);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(P->gstream, &g);
+        P->s = saved;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) { ge = nullptr; return hip_fail(e, "hipGraphInstantiate"); }
+    }
+    hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(1), 0, P->s, P->iterdev, tau, sigma, (long long)k0);
+    HIPCHK(hipGraphLaunch(ge, P->s));
+    return DPDLP_OK;
+}
+
+static void drop_graphs(dpdlp_problem *P)
+{
+    for (auto &g : P->graph)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
 // Check passes at (xh, yh, dx, dy) against the anchor (xa_any, ya_any).
@@ -781,7 +831,15 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     dpdlp_problem *P = new dpdlp_problem();
     std::unique_ptr<dpdlp_problem> guard(P);
     if (params) P->prm = *params; else dpdlp_params_default(&P->prm);
-    if (P->prm.tile_nnz <= 0 || P->prm.tile_nnz > kTileNnzMax) P->prm.tile_nnz = kTileNnzMax;
+    if (P->prm.tile_nnz <= 0) {
+        // automatic: enough tiles for ~8 workgroups per CU (256 CUs), 256..2048
+        const int64_t nz = lp.row_ptr[lp.m];
+        int64_t tn = nz / (256 * 8);
+        int32_t p2 = 256;
+        while (p2 < tn && p2 < kTileNnzMax) p2 <<= 1;
+        P->prm.tile_nnz = p2;
+    }
+    if (P->prm.tile_nnz > kTileNnzMax) P->prm.tile_nnz = kTileNnzMax;
     if (P->prm.check_period < 1) P->prm.check_period = 1;
     P->s = (hipStream_t)stream;
     P->m = lp.m; P->n = lp.n; P->nnz = lp.row_ptr[lp.m];
@@ -854,6 +912,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     CHK(dalloc(P, &P->sig_hist, (size_t)std::max(1, P->prm.power_max_iters) + 2));
     CHK(dalloc(P, &P->ctl, 1));
     CHK(dalloc(P, &P->ctl_eval, 1));
+    CHK(dalloc(P, &P->iterdev, 1));
     HIPCHK(hipHostMalloc((void **)&P->h_ctl, sizeof(Control), hipHostMallocDefault));
 
     // A3: rescaling (Ruiz passes, then one Pock-Chambolle pass)
@@ -1000,6 +1059,18 @@ static int iterate_impl(dpdlp_problem *P, int64_t n_iters)
         if (P->t >= P->prm.max_iters) { P->status = DPDLP_ITER_LIMIT; break; }
         const double tau = P->eta / P->omega, sigma = P->eta * P->omega;
         const bool is_check = (P->k == 0) || ((P->t + 1) % K == 0);
+        if (!is_check && P->prm.use_graphs && !P->prof && K > 1 && P->t % K == 0) {
+            // a whole run t .. t+K-2 of non-check iterations, none the last of the call
+            const int L = K - 1;
+            if (done + L < n_iters && P->t + L < P->prm.max_iters) {
+                CHK(run_graph(P, tau, sigma, P->k, L));
+                if (P->in_fp32) P->fp32_iters += L;
+                done += L;
+                P->k += L;
+                P->t += L;
+                continue;
+            }
+        }
         const bool last = (done + 1 == n_iters) || (P->t + 1 >= P->prm.max_iters);
         pdhg_iteration(P, tau, sigma, P->k, (is_check || last) ? 1 : 0);
         if (P->in_fp32) P->fp32_iters++;
@@ -1202,6 +1273,8 @@ int dpdlp_problem_destroy(dpdlp_problem *P)
     for (int c = 0; c < 8; ++c)
         for (auto &pr : P->ev[c]) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto e : P->ev_pool) (void)hipEventDestroy(e);
+    drop_graphs(P);
+    if (P->gstream) (void)hipStreamDestroy(P->gstream);
     delete P;
     return DPDLP_OK;
 }
@@ -1216,6 +1289,8 @@ int dpdlp_set_params(dpdlp_problem *P, const dpdlp_params *q)
     p.beta_suf = q->beta_suf; p.beta_nec = q->beta_nec; p.beta_art = q->beta_art;
     p.kp = q->kp; p.ki = q->ki; p.kd = q->kd; p.xcd_remap = q->xcd_remap;
     p.fp32_switch_tol = q->fp32_switch_tol; p.fp32_stall_checks = q->fp32_stall_checks;
+    p.use_graphs = q->use_graphs;
+    drop_graphs(P);                 // gamma is a captured kernel argument
     return DPDLP_OK;
 }
 

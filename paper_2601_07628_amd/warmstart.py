@@ -8,9 +8,10 @@ Protocol:
   1. solve every training instance with the FP64 solver to eps (targets);
   2. reference point = mean of the training solutions (and of c, b);
   3. train the network (residual on the reference point) with Adam;
-  4. for a held-out instance: predict (x0, y0); judge it by its relative KKT
-     error against the cold start (0 clamped into X, 0 projected onto Y);
-     start from the better one; if a warm run does not converge within its
+  4. for a held-out instance: predict (x0, y0); judge the prediction, its
+     primal part alone and its dual part alone by the relative KKT error of
+     the start point against the cold start (0 clamped into X, 0 projected
+     onto Y); start from the best; if a warm run does not converge within its
      iteration cap, a cold run takes over.
 """
 from __future__ import annotations
@@ -103,32 +104,41 @@ def warm_solve(prob: Problem, inst, mode: str, net: Optional[WarmStartNet] = Non
                ref=None, warm_cap: Optional[int] = None) -> dict:
     """Solve one member from a cold, mean-reference or network start.
 
-    The predicted start is judged by its KKT error against the cold start;
-    the worse one is discarded.  A warm run that does not converge within
+    Judge: the candidate starts (x0, y0), (x0, cold y), (cold x, y0) and the
+    cold start are scored by the relative KKT error of the point the solver
+    would start from; the best one is used, so a prediction is used only
+    where it beats the cold start.  A warm run that does not converge within
     warm_cap iterations is followed by a cold run (both are counted)."""
     prob.update_data(inst.c, inst.con_lo, inst.con_hi)
     t0 = time.perf_counter()
     x0 = y0 = None
-    fallback = False
-    kw = kc = None
     if mode == "gnn":
         net.set_instance(inst.c, inst.con_lo, inst.con_hi)
         x0, y0 = net.forward()
     elif mode == "mean":
         x0, y0 = ref[2], ref[3]
+    kw = kc = None
+    choice = "cold"
     if x0 is not None:
-        kw = start_kkt(prob, x0, y0)
         kc = start_kkt(prob)
-        if not kw < kc:
+        cands = {"both": (x0, y0), "primal": (x0, None), "dual": (None, y0)}
+        scores = {k: start_kkt(prob, *v) for k, v in cands.items()}
+        best = min(scores, key=scores.get)
+        kw = scores[best]
+        if kw < kc:
+            choice = best
+            x0, y0 = cands[best]
+        else:
             x0 = y0 = None
-            fallback = True
+    fallback = choice == "cold" and mode != "cold"
     saved = prob.params.max_iters
     total_iters = 0
-    if x0 is not None and warm_cap:
+    warm = x0 is not None or y0 is not None
+    if warm and warm_cap:
         prob.set_params(max_iters=warm_cap)
     r = prob.solve(x0, y0)
     total_iters += r["iters"]
-    if r["status"] != CONVERGED and x0 is not None:
+    if r["status"] != CONVERGED and warm:
         prob.set_params(max_iters=saved)
         r = prob.solve()
         total_iters += r["iters"]
@@ -136,5 +146,5 @@ def warm_solve(prob: Problem, inst, mode: str, net: Optional[WarmStartNet] = Non
     prob.set_params(max_iters=saved)
     el = time.perf_counter() - t0
     return dict(mode=mode, iters=int(total_iters), seconds=el, status=int(r["status"]),
-                fallback=fallback, kkt_warm=kw, kkt_cold=kc, obj=r["obj_primal"],
-                kkt=max(r["r_primal"], r["r_dual"], r["r_gap"]))
+                fallback=fallback, choice=choice, kkt_warm=kw, kkt_cold=kc,
+                obj=r["obj_primal"], kkt=max(r["r_primal"], r["r_dual"], r["r_gap"]))

@@ -332,3 +332,20 @@ def test_bad_input_is_rejected_on_gpu(D):
     with pytest.raises(D.DpdlpError) as e:
         D.Problem(lp)
     assert e.value.code == D.E_BAD_CSR
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(precision=1), dict(gather_slices=8)])
+def test_graph_replay_matches_eager_bitwise(D, kw):
+    """Runs between checks replayed as one HIP graph give bitwise the same
+    solve as eager launches (dozens of replays with restarts, checks and host
+    synchronizations between them)."""
+    lp = lpgen.config4()
+    outs = []
+    for graphs in (0, 1):
+        G = D.Problem(lp, gpu_params(D, use_graphs=graphs, **kw))
+        r = G.solve()
+        outs.append((r, G.log()))
+    (r0, l0), (r1, l1) = outs
+    assert r0["status"] == 1 and r0["iters"] == r1["iters"]
+    assert np.array_equal(r0["x"], r1["x"]) and np.array_equal(r0["y"], r1["y"])
+    assert [e["restart"] for e in l0] == [e["restart"] for e in l1]
