@@ -177,6 +177,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--no-c1-ttt", action="store_true",
+                    help="skip the capped time-to-1e-4 solves on config 1")
     ap.add_argument("--ws-train", type=int, default=16,
                     help="warm-start family members used for training (full protocol: 384)")
     ap.add_argument("--ws-test", type=int, default=4,
@@ -271,6 +273,8 @@ def main():
     del G
 
     def sliced(S):
+        # S = 0: no slicing; S = 8: both steps sliced (the default slices only
+        # where it pays)
         GS = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9, gather_slices=S),
                        stream=stream)
         GS.init()
@@ -279,11 +283,11 @@ def main():
         nst = max(5, args.steps // 2)
         elS = timed_steps(GS, nst, ips, torch)
         pS = GS.profile()
-        extra[f"fp64_xcd_sliced_{S}"] = {
+        extra[f"fp64_gather_slices_{S}"] = {
             "iters_per_s": round(nst * ips / elS, 1),
             "primal_ms": round(pS["primal"]["total_ms"] / max(pS["primal"]["launches"], 1), 4),
             "dual_ms": round(pS["dual"]["total_ms"] / max(pS["dual"]["launches"], 1), 4)}
-        log(f"FP64 XCD-sliced S={S}: {extra[f'fp64_xcd_sliced_{S}']}")
+        log(f"FP64 gather_slices={S}: {extra[f'fp64_gather_slices_{S}']}")
         GS.close()
 
     def fp32():
@@ -307,6 +311,26 @@ def main():
             "fp32_mixed": time_to_tol(D, inst, torch, precision=D.FP32_MIXED)}
         log(f"time-to-tolerance {name}: {extra[f'time_to_tol_{name}']}")
 
+    def c1_ttt():
+        out = {}
+        for name, kw in (("fp64", {}), ("fp32_mixed", {"precision": D.FP32_MIXED})):
+            Gt = D.Problem(lp, gpu_params(D, eps=1e-4, max_iters=10**9, time_limit=45.0, **kw),
+                           stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = Gt.solve()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[name] = {"seconds": round(el, 3), "iters": int(r["iters"]),
+                         "status": D.dpdlp_status_string(r["status"]),
+                         "kkt": max(r["r_primal"], r["r_dual"], r["r_gap"]),
+                         "obj": r["obj_primal"], "fp32_iters": int(r["fp32_iters"]),
+                         "setup_s": round(r["setup_seconds"], 3)}
+            Gt.close()
+        out["obj_constructed"] = lp.obj_star
+        extra["time_to_1e-4_c1"] = out
+        log(f"c1 time to 1e-4 (45 s cap): {out}")
+
     def ws():
         full = args.ws_train >= 384
         extra["warm_start_c4"] = warmstart_eval(
@@ -314,11 +338,13 @@ def main():
             eps_list=(1e-6, 1e-8) if full else (1e-8,))
 
     if not args.no_extra:
-        for S in (8, 16):
-            guarded(f"fp64_xcd_sliced_{S}", lambda S=S: sliced(S))
+        for S in (0, 8):
+            guarded(f"fp64_gather_slices_{S}", lambda S=S: sliced(S))
         guarded("fp32_mixed_c1", fp32)
         for name, mk in (("c0", lpgen.config0), ("c4", lpgen.config4)):
             guarded(f"time_to_tol_{name}", lambda name=name, mk=mk: ttt(name, mk))
+        if not args.no_c1_ttt:
+            guarded("time_to_1e-4_c1", c1_ttt)
         if not args.no_warmstart:
             guarded("warm_start_c4", ws)
 

@@ -94,13 +94,19 @@ typedef struct dpdlp_params {
     uint64_t perm_seed;       /* seed of the block permutation               */
     int32_t precision;        /* DPDLP_FP64 or DPDLP_FP32_MIXED              */
     int32_t xcd_remap;        /* 1: map consecutive tiles onto one XCD        */
-    double fp32_switch_tol;   /* FP32 -> FP64 switch when KKT <= this (1e-6) */
-    int32_t fp32_stall_checks;/* ... or no 2x KKT improvement in this many checks (8) */
-    int32_t gather_slices;    /* 0: off; S (multiple of 8, <= 64): cut the    */
-                              /* gathered dimension of each fused step into S */
-                              /* slices, slice s on XCD s % 8, partial sums   */
-                              /* added per segment in slice order (the 2-D    */
-                              /* partition of Sec. 3.1 across the 8 XCDs)     */
+    double fp32_switch_tol;   /* FP32 -> FP64 switch when KKT <= this (1e-6); */
+                              /* the KKT is always evaluated in FP64, so an  */
+                              /* FP32 iterate with KKT <= eps ends the solve */
+    int32_t fp32_stall_checks;/* ... or no 2x KKT improvement in this many checks (64) */
+    int32_t gather_slices;    /* -1 (default): automatic; 0: off; S (multiple */
+                              /* of 8, <= 64): cut the gathered dimension of */
+                              /* each fused step into S slices, slice s on   */
+                              /* XCD s % 8, partial sums added per segment in */
+                              /* slice order (the 2-D partition of Sec. 3.1  */
+                              /* across the 8 XCDs).  Automatic slices a step */
+                              /* (S = 8) when its gathered vector exceeds 4 MB */
+                              /* and its 8 partials per segment cost under a  */
+                              /* third of its 12 bytes per nonzero.           */
     int32_t use_graphs;       /* 1: replay the check_period - 1 iterations    */
                               /* between two checks as one HIP graph (off    */
                               /* while dpdlp_profile_enable is on)           */

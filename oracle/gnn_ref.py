@@ -94,18 +94,22 @@ def relu(z):
     return np.maximum(z, 0.0)
 
 
-def forward(p, layers, A: sp.csr_matrix, Xc, Xr, xref_s, yref_s):
+def forward(p, layers, A: sp.csr_matrix, Xc, Xr, xref_s, yref_s, rnd=None):
+    """rnd (optional) is applied to every stored activation (H and the
+    products S), e.g. a rounding to the storage format of an implementation;
+    the gradient then treats it as the identity."""
+    rnd = rnd or (lambda v: v)
     W = unpack(p, layers)
     At = A.T.tocsr()
     cache = {"INc": [], "INr": [], "Hc": [], "Hr": []}
-    Hc = relu(Xc @ W["W_cin"])
-    Hr = relu(Xr @ W["W_rin"])
+    Hc = rnd(relu(Xc @ W["W_cin"]))
+    Hr = rnd(relu(Xr @ W["W_rin"]))
     cache["Hc0"], cache["Hr0"] = Hc, Hr
     for l in range(layers):
-        INr = np.hstack([Hr, A @ Hc])
-        Hr = relu(INr @ W["W_r"][l])
-        INc = np.hstack([Hc, At @ Hr])
-        Hc = relu(INc @ W["W_c"][l])
+        INr = np.hstack([Hr, rnd(A @ Hc)])
+        Hr = rnd(relu(INr @ W["W_r"][l]))
+        INc = np.hstack([Hc, rnd(At @ Hr)])
+        Hc = rnd(relu(INc @ W["W_c"][l]))
         cache["INr"].append(INr)
         cache["INc"].append(INc)
         cache["Hr"].append(Hr)
@@ -115,11 +119,11 @@ def forward(p, layers, A: sp.csr_matrix, Xc, Xr, xref_s, yref_s):
     return px, py, cache
 
 
-def loss_and_grad(p, layers, A: sp.csr_matrix, Xc, Xr, xref_s, yref_s, tx_s, ty_s):
+def loss_and_grad(p, layers, A: sp.csr_matrix, Xc, Xr, xref_s, yref_s, tx_s, ty_s, rnd=None):
     """Loss and its gradient with respect to the flat parameter vector."""
     W = unpack(p, layers)
     At = A.T.tocsr()
-    px, py, cache = forward(p, layers, A, Xc, Xr, xref_s, yref_s)
+    px, py, cache = forward(p, layers, A, Xc, Xr, xref_s, yref_s, rnd)
     n, m = px.size, py.size
     rx, ry = px - tx_s, py - ty_s
     loss = (rx @ rx) / n + (ry @ ry) / m

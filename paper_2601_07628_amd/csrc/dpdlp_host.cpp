@@ -324,8 +324,8 @@ void dpdlp_params_default(dpdlp_params *p)
     p->precision = DPDLP_FP64;
     p->xcd_remap = 1;
     p->fp32_switch_tol = 1e-6;
-    p->fp32_stall_checks = 8;
-    p->gather_slices = 0;
+    p->fp32_stall_checks = 64;
+    p->gather_slices = -1;
     p->use_graphs = 1;
 }
 

@@ -757,6 +757,39 @@ static int power_iteration(dpdlp_problem *P)
     return DPDLP_OK;
 }
 
+// Every device buffer a kernel of the solve path writes or reads must be
+// allocated; a missing one is reported here instead of reaching a kernel.
+static int check_buffers(dpdlp_problem *P)
+{
+    const void *req[] = {P->rp, P->ci, P->v, P->cp, P->ri, P->vt, P->tr.d, P->tc.d, P->carries,
+                         P->part_r, P->part_c, P->perm_row, P->perm_col, P->c0, P->clo0,
+                         P->chi0, P->vlo0, P->vhi0, P->c, P->clo, P->chi, P->vlo, P->vhi, P->dr,
+                         P->dc, P->fr, P->fc, P->x, P->y, P->xbar, P->xa, P->ya, P->xh, P->yh,
+                         P->dx, P->dy, P->tmp_m, P->tmp_n, P->tmp_m2, P->tmp_n2, P->scal,
+                         P->sig_hist, P->ctl, P->ctl_eval, P->iterdev, P->h_ctl};
+    for (const void *p : req)
+        if (!p) { set_error("internal: a device buffer is not allocated"); return DPDLP_E_HIP; }
+    if ((P->tr.nsplit && !P->tr.splits) || (P->tc.nsplit && !P->tc.splits)) {
+        set_error("internal: split list not allocated");
+        return DPDLP_E_HIP;
+    }
+    for (const SlicedSet *ss : {&P->sr, &P->sc})
+        if (ss->S > 0 && (!ss->ptr || !ss->idx || !ss->val || !ss->ts.d || !ss->ts.blk2tile ||
+                          !P->part_slices || (ss->ts.nsplit && !ss->ts.splits))) {
+            set_error("internal: sliced buffers not allocated");
+            return DPDLP_E_HIP;
+        }
+    if (P->prm.precision == DPDLP_FP32_MIXED) {
+        const void *r32[] = {P->v32, P->vt32, P->x32, P->y32, P->xbar32, P->xa32, P->ya32,
+                             P->c32, P->clo32, P->chi32, P->vlo32, P->vhi32};
+        for (const void *p : r32)
+            if (!p) { set_error("internal: FP32 buffer not allocated"); return DPDLP_E_HIP; }
+        for (const SlicedSet *ss : {&P->sr, &P->sc})
+            if (ss->S > 0 && !ss->val32) { set_error("internal: FP32 sliced values"); return DPDLP_E_HIP; }
+    }
+    return DPDLP_OK;
+}
+
 // Scaled problem vectors (c~, bounds) and the norms used by the KKT
 // denominators and omega0, from the permuted original vectors and D_r, D_c.
 static int scale_data(dpdlp_problem *P)
@@ -867,17 +900,30 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     CHK(build_tileset(P, H.rp, m, P->tr, ht));
     CHK(build_tileset(P, H.cp, n, P->tc, ht));
     int ntmax = std::max(P->tr.n, P->tc.n);
-    const int S = P->prm.gather_slices;
-    if (S > 0) {
-        if (S % 8 != 0 || S > 64) {
-            set_error("gather_slices must be 0 or a multiple of 8 up to 64");
+    // XCD-sliced fused steps: S > 0 slices both steps; S < 0 (automatic)
+    // slices a step with S = 8 when its gathered vector exceeds one XCD's L2
+    // (4 MB) and its partial sums (8 per segment) cost under a third of its
+    // matrix stream (12 bytes per nonzero).
+    int Sd = 0, Sp = 0;                 // dual (CSR, gathers x), primal (CSC, gathers y)
+    if (P->prm.gather_slices > 0) {
+        if (P->prm.gather_slices % 8 != 0 || P->prm.gather_slices > 64) {
+            set_error("gather_slices must be -1, 0 or a multiple of 8 up to 64");
             return DPDLP_E_INVALID_ARG;
         }
-        CHK(build_sliced(P, H.rp, H.ci, m, n, S, P->sr));     // dual: gathers xbar
-        CHK(build_sliced(P, H.cp, H.ri, n, m, S, P->sc));     // primal: gathers y
-        ntmax = std::max(ntmax, std::max(P->sr.ts.n, P->sc.ts.n));
-        CHK(dalloc(P, (double **)&P->part_slices, (size_t)S * std::max(m, n)));
+        Sd = Sp = P->prm.gather_slices;
+    } else if (P->prm.gather_slices < 0) {
+        const double mat = 12.0 * (double)nnz;
+        if (8.0 * n > 4.0 * (1 << 20) && 8.0 * 8.0 * m < mat / 3.0) Sd = 8;
+        if (8.0 * m > 4.0 * (1 << 20) && 8.0 * 8.0 * n < mat / 3.0) Sp = 8;
     }
+    if (Sd) CHK(build_sliced(P, H.rp, H.ci, m, n, Sd, P->sr));     // dual: gathers xbar
+    if (Sp) CHK(build_sliced(P, H.cp, H.ri, n, m, Sp, P->sc));     // primal: gathers y
+    if (Sd || Sp) {
+        ntmax = std::max(ntmax, std::max(P->sr.ts.n, P->sc.ts.n));
+        const size_t ps = std::max((size_t)Sd * m, (size_t)Sp * n);
+        CHK(dalloc(P, (double **)&P->part_slices, ps));
+    }
+    // split-piece carries (2 right-hand sides) and per-tile partial sums
     CHK(dalloc(P, (double **)&P->carries, (size_t)2 * std::max(ntmax, 1)));
     CHK(dalloc(P, &P->part_r, (size_t)kNQ * std::max(P->tr.n, 1)));
     CHK(dalloc(P, &P->part_c, (size_t)kNQ * std::max(P->tc.n, 1)));
@@ -945,12 +991,12 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         apply_scale();
     }
     CHK(scale_data(P));
-    if (P->prm.gather_slices > 0) {
+    if (P->sr.S > 0)
         hipLaunchKernelGGL(k_gather_vals<double>, dim3(nblk((int64_t)nnz)), dim3(kBlock), 0, P->s,
                            P->sr.src, P->v, P->sr.val, (int64_t)nnz);
+    if (P->sc.S > 0)
         hipLaunchKernelGGL(k_gather_vals<double>, dim3(nblk((int64_t)nnz)), dim3(kBlock), 0, P->s,
                            P->sc.src, P->vt, P->sc.val, (int64_t)nnz);
-    }
     // A4: step size
     if (P->prm.eta > 0) {
         P->eta = P->prm.eta;
@@ -971,14 +1017,13 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
             if (k) hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(k)), dim3(kBlock), 0, P->s, a, b, k);
         };
         cv(P->v, P->v32, (int64_t)nnz); cv(P->vt, P->vt32, (int64_t)nnz);
-        if (P->prm.gather_slices > 0) {
-            CHK(dalloc(P, &P->sr.val32, nnz)); CHK(dalloc(P, &P->sc.val32, nnz));
-            cv(P->sr.val, P->sr.val32, (int64_t)nnz); cv(P->sc.val, P->sc.val32, (int64_t)nnz);
-        }
+        if (P->sr.S > 0) { CHK(dalloc(P, &P->sr.val32, nnz)); cv(P->sr.val, P->sr.val32, (int64_t)nnz); }
+        if (P->sc.S > 0) { CHK(dalloc(P, &P->sc.val32, nnz)); cv(P->sc.val, P->sc.val32, (int64_t)nnz); }
         CHK(scale_data(P));
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(P->s));
+    CHK(check_buffers(P));
     P->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     *out = guard.release();
     return DPDLP_OK;
@@ -1093,12 +1138,7 @@ static int iterate_impl(dpdlp_problem *P, int64_t n_iters)
         rec.omega = P->omega; rec.restart = C.restart;
         P->log.push_back(rec);
         if (C.numerical) { P->status = DPDLP_NUMERICAL; P->t++; break; }
-        if (C.converged) {
-            if (P->in_fp32) {        // FP32 result: polish in FP64 before stopping
-                CHK(switch_to_fp64(P));
-                P->t++;
-                continue;
-            }
+        if (C.converged) {           // the KKT is evaluated in FP64 in both precisions
             P->status = DPDLP_CONVERGED;
             P->t++;
             break;

@@ -34,9 +34,10 @@ def _col(header, *names):
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"k_tile<dpdlp::(\w+)(?:<(\w+)>)?", name)
+    m = re.search(r"(k_\w+)<dpdlp::(\w+)(?:<\s*(\w+)\s*>)?", name)
     if m:
-        return f"k_tile<{m.group(1)}{'<' + m.group(2) + '>' if m.group(2) else ''}>"
+        inner = m.group(2) + (f"<{m.group(3)}>" if m.group(3) else "")
+        return f"{m.group(1)}<{inner}>"
     m = re.search(r"(k_\w+)", name)
     if m:
         return m.group(1)
@@ -59,7 +60,8 @@ def read_trace(path):
 
 
 def read_counter(path, counter):
-    """{kernel name: [values per dispatch, in dispatch order]}"""
+    """[(dispatch id, kernel name, value)] in dispatch order (values of one
+    dispatch summed over the counter's instances)."""
     with open(path) as f:
         rows = list(csv.reader(f))
     h = rows[0]
@@ -67,12 +69,49 @@ def read_counter(path, counter):
     i_cn = _col(h, "counter_name")
     i_cv = _col(h, "counter_value")
     i_d = _col(h, "dispatch_id")
-    per = defaultdict(dict)
+    per = {}
     for r in rows[1:]:
         if r[i_cn] != counter:
             continue
-        per[r[i_n]][int(r[i_d])] = per[r[i_n]].get(int(r[i_d]), 0.0) + float(r[i_cv])
-    return {k: [v[d] for d in sorted(v)] for k, v in per.items()}
+        d = int(r[i_d])
+        name, v = per.get(d, (r[i_n], 0.0))
+        per[d] = (name, v + float(r[i_cv]))
+    return [(d, per[d][0], per[d][1]) for d in sorted(per)]
+
+
+def step_of(name):
+    """Which fused step a kernel belongs to: ('primal' | 'dual', is_head),
+    'partial' for the per-slice partial sums (the step is named by the
+    combine that follows), or None."""
+    for op, step in (("PrimalOp<double>", "primal"), ("DualOp<double>", "dual")):
+        if op in name:
+            head = "k_tile<" in name or "k_combine<" in name
+            return step, head
+    if "PartialOp<double>" in name:
+        return "partial"
+    return None
+
+
+def per_step_bytes(disp):
+    """Mean KiB per launch of each fused FP64 step.  A step is the tile
+    kernel and its split-segment fix-up or, in the XCD-sliced form, the
+    per-slice partial kernels, their fix-up and the combine kernel."""
+    tot, launches, pending = defaultdict(float), defaultdict(int), 0.0
+    for _, name, v in disp:
+        s = step_of(name)
+        if s is None:
+            continue
+        if s == "partial":
+            pending += v
+            continue
+        step, head = s
+        tot[step] += v
+        if "k_combine<" in name:
+            tot[step] += pending
+            pending = 0.0
+        if head:
+            launches[step] += 1
+    return {k: (tot[k] / launches[k], launches[k]) for k in launches}
 
 
 def kernel_source_hash(root):
@@ -88,30 +127,33 @@ def kernel_source_hash(root):
 def traffic(fetch_csv, write_csv, workload):
     fe = read_counter(fetch_csv, "FETCH_SIZE")
     wr = read_counter(write_csv, "WRITE_SIZE")
-    copy = [k for k in fe if "copy" in k.lower()]
-    if not copy:
-        raise SystemExit("no calibration copy kernel found in the FETCH_SIZE run")
+
+    def first_copy(disp):
+        for _, name, v in disp:
+            if "copy" in name.lower():
+                return name, v
+        raise SystemExit("no calibration copy kernel found in the counter run")
     # the first copy dispatch is the 256 MiB calibration copy
-    cal_f = CALIB_BYTES / (fe[copy[0]][0] * 1024.0)
-    wc = [k for k in wr if "copy" in k.lower()]
-    cal_w = CALIB_BYTES / (wr[wc[0]][0] * 1024.0)
-    out = {"calibration": {"copy_kernel": short_name(copy[0]),
+    cname, cf = first_copy(fe)
+    _, cw = first_copy(wr)
+    cal_f, cal_w = CALIB_BYTES / (cf * 1024.0), CALIB_BYTES / (cw * 1024.0)
+    out = {"calibration": {"copy_kernel": short_name(cname),
                            "fetch_factor": cal_f, "write_factor": cal_w}, "kernels": {}}
-    for name, vals in fe.items():
-        key = None
-        if "PrimalOp<double>" in name:
-            key = "primal"
-        elif "DualOp<double>" in name:
-            key = "dual"
-        if key is None:
-            continue
-        wv = wr.get(name, [])
-        f_b = sum(vals) / len(vals) * 1024.0 * cal_f
-        w_b = (sum(wv) / len(wv) * 1024.0 * cal_w) if wv else 0.0
-        out["kernels"][f"{workload}/{key}"] = {
-            "dispatches": len(vals), "fetch_bytes_per_launch": f_b,
-            "write_bytes_per_launch": w_b, "bytes_per_launch": f_b + w_b,
-            "kernel": short_name(name)}
+    sf, sw = per_step_bytes(fe), per_step_bytes(wr)
+    for step, (f_kib, n) in sf.items():
+        w_kib = sw.get(step, (0.0, 0))[0]
+        f_b, w_b = f_kib * 1024.0 * cal_f, w_kib * 1024.0 * cal_w
+        out["kernels"][f"{workload}/{step}"] = {
+            "launches": n, "fetch_bytes_per_launch": f_b,
+            "write_bytes_per_launch": w_b, "bytes_per_launch": f_b + w_b}
+    per_kernel = defaultdict(list)
+    for _, name, v in fe:
+        per_kernel[short_name(name)].append(v)
+    out["fetch_kib_per_dispatch"] = {k: round(sum(v) / len(v), 1) for k, v in per_kernel.items()}
+    per_kernel = defaultdict(list)
+    for _, name, v in wr:
+        per_kernel[short_name(name)].append(v)
+    out["write_kib_per_dispatch"] = {k: round(sum(v) / len(v), 1) for k, v in per_kernel.items()}
     return out
 
 

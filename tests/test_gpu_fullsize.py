@@ -1,6 +1,7 @@
 """Parity at the full sizes of the benchmark workloads, in the launch
 configuration bench.py times (default parameters: 2048-nonzero tiles, XCD
-remap on, block permutation B = 256; plus the XCD-sliced form).
+remap on, block permutation B = 256, automatic XCD slicing, which slices
+c1's dual step), plus slicing off and slicing of both steps.
 
 c1 (m 2M, n 4M, 40M nonzeros) and c2 (m 6000, n 9M, 18M nonzeros): both
 sides run the first iterations from the same start with the same eta and
@@ -53,7 +54,7 @@ def _fullsize(D, lp, n_iters, slices=0):
             assert abs(g[q] - o[q]) <= 1e-9 * abs(o[q]) + 1e-300, (q, g[q], o[q])
 
 
-@pytest.mark.parametrize("slices", [0, 8])
+@pytest.mark.parametrize("slices", [0, -1, 8])
 def test_c1_fullsize_parity(D, slices):
     _fullsize(D, lpgen.config1(), 3, slices)
 

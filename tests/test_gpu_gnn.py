@@ -96,7 +96,7 @@ def test_gnn_forward_and_gradient_match_fp64_reference(D):
 
     # reference, from the oracle's own scaling of the same matrix, evaluated
     # with the network's BF16 weight matrices and BF16 input features (the
-    # heads are FP32 on the GPU); activations stay FP64 in the reference
+    # heads are FP32 on the GPU)
     P = oracle.Problem(base, oracle.Params(eta=1.0, omega0=1.0))
     sd = P.scaled()
     dr, dc = sd["dr"], sd["dc"]
@@ -107,21 +107,25 @@ def test_gnn_forward_and_gradient_match_fp64_reference(D):
     Xr = bf16_value(bf16_bits(Xr)).reshape(Xr.shape)
     pq = p.astype(np.float64)
     pq[:-256] = bf16_value(bf16_bits(p[:-256]))
-    px, py, _ = gnn_ref.forward(pq, layers, A, Xc, Xr, x_ref / dc, y_ref / dr)
+    rnd = lambda v: bf16_value(bf16_bits(v)).reshape(v.shape)
     rel = lambda a, b: np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
-    # predictions: compare the learned correction (prediction minus reference)
-    assert rel(x0 / dc - x_ref / dc, px - x_ref / dc) < 3e-2
-    assert rel(y0 / dr - y_ref / dr, py - y_ref / dr) < 3e-2
-    L, gr = gnn_ref.loss_and_grad(pq, layers, A, Xc, Xr, x_ref / dc, y_ref / dr,
-                                  tx / dc, ty / dr)
-    assert abs(loss.sum() - L) <= 2e-2 * L
-    d_g, d_r = gnn_ref.unpack(g, layers), gnn_ref.unpack(gr, layers)
     blocks = [("W_cin", None), ("W_rin", None), ("w_x", None), ("w_y", None)]
     blocks += [("W_c", l) for l in range(layers)] + [("W_r", l) for l in range(layers)]
-    for name, l in blocks:
-        a = d_g[name] if l is None else d_g[name][l]
-        b = d_r[name] if l is None else d_r[name][l]
-        assert rel(a, b) < 5e-2, (name, l, rel(a, b))
+    # (1) the same network: FP64 arithmetic with the GPU's BF16 activation
+    #     storage; (2) plain FP64 activations (shows the effect of BF16)
+    for act, tol_pred, tol_grad in ((rnd, 1e-2, 2e-2), (None, 3e-2, 1e-1)):
+        px, py, _ = gnn_ref.forward(pq, layers, A, Xc, Xr, x_ref / dc, y_ref / dr, act)
+        # predictions: compare the learned correction (prediction minus reference)
+        assert rel(x0 / dc - x_ref / dc, px - x_ref / dc) < tol_pred
+        assert rel(y0 / dr - y_ref / dr, py - y_ref / dr) < tol_pred
+        L, gr = gnn_ref.loss_and_grad(pq, layers, A, Xc, Xr, x_ref / dc, y_ref / dr,
+                                      tx / dc, ty / dr, act)
+        assert abs(loss.sum() - L) <= tol_pred * L
+        d_g, d_r = gnn_ref.unpack(g, layers), gnn_ref.unpack(gr, layers)
+        for name, l in blocks:
+            a = d_g[name] if l is None else d_g[name][l]
+            b = d_r[name] if l is None else d_r[name][l]
+            assert rel(a, b) < tol_grad, (act is not None, name, l, rel(a, b))
 
 
 def test_gnn_training_reduces_loss_and_is_deterministic(D):
