@@ -97,7 +97,11 @@ typedef struct dpdlp_params {
     double fp32_switch_tol;   /* FP32 -> FP64 switch when KKT <= this (1e-6); */
                               /* the KKT is always evaluated in FP64, so an  */
                               /* FP32 iterate with KKT <= eps ends the solve */
-    int32_t fp32_stall_checks;/* ... or no 2x KKT improvement in this many checks (64) */
+    int32_t fp32_stall_checks;/* ... or no 2x KKT improvement in this many checks (64), */
+                              /* or divergence (fp32_diverge below); FP64   */
+                              /* resumes as a fresh epoch at the last check */
+                              /* point, after a divergence at the FP32      */
+                              /* phase's best one with its primal weight    */
     int32_t gather_slices;    /* -1 (default): automatic; 0: off; S (multiple */
                               /* of 8, <= 64): cut the gathered dimension of */
                               /* each fused step into S slices, slice s on   */
@@ -110,7 +114,19 @@ typedef struct dpdlp_params {
     int32_t use_graphs;       /* 1: replay the check_period - 1 iterations    */
                               /* between two checks as one HIP graph (off    */
                               /* while dpdlp_profile_enable is on)           */
+    int32_t perm_order;       /* 0: the block-wise random permutation alone; */
+                              /* bit 0 (rows) / bit 1 (columns): hot-first, */
+                              /* that order stably sorted by decreasing     */
+                              /* nonzero count, so the most gathered entries */
+                              /* of y / x share cache lines; automatic      */
+                              /* slicing then leaves that gather unsliced   */
+                              /* (equal index ranges would put most         */
+                              /* nonzeros in one slice); values above 3 are  */
+                              /* rejected                                   */
     int32_t pad1;
+    double fp32_diverge;      /* FP32 -> FP64 switch when the KKT exceeds    */
+                              /* this multiple of the FP32 phase's best (10; */
+                              /* 0: off)                                    */
 } dpdlp_params;
 
 typedef struct dpdlp_result {

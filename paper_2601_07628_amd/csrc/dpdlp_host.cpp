@@ -199,7 +199,7 @@ void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &i
 }
 
 void permute_and_transpose(const dpdlp_csr_lp *lp, int32_t block, uint64_t seed,
-                           HostMatrix &H)
+                           int32_t order, HostMatrix &H)
 {
     const int32_t m = lp->m, n = lp->n;
     H.m = m; H.n = n;
@@ -208,6 +208,22 @@ void permute_and_transpose(const dpdlp_csr_lp *lp, int32_t block, uint64_t seed,
     H.perm_col.resize((size_t)n);
     block_permutation(m, block, seed, H.perm_row.data());
     block_permutation(n, block, seed ^ 0xC01D5EEDull, H.perm_col.data());
+    // hot-first (order bit 0: rows, bit 1: columns): a stable sort of the
+    // block-permuted order by decreasing nonzero count, so that the entries
+    // gathered most often share cache lines at the front of y (or x); equal
+    // counts keep their block-random order
+    if (order & 1) {
+        std::vector<int32_t> rc((size_t)m);
+        for (int32_t i = 0; i < m; ++i) rc[(size_t)i] = lp->row_ptr[i + 1] - lp->row_ptr[i];
+        std::stable_sort(H.perm_row.begin(), H.perm_row.end(),
+                         [&](int32_t a, int32_t b) { return rc[(size_t)a] > rc[(size_t)b]; });
+    }
+    if (order & 2) {
+        std::vector<int32_t> cc((size_t)n, 0);
+        for (int64_t p = 0; p < H.nnz; ++p) cc[(size_t)lp->col_idx[p]]++;
+        std::stable_sort(H.perm_col.begin(), H.perm_col.end(),
+                         [&](int32_t a, int32_t b) { return cc[(size_t)a] > cc[(size_t)b]; });
+    }
     std::vector<int32_t> inv_col((size_t)n);
     for (int32_t j = 0; j < n; ++j) inv_col[(size_t)H.perm_col[(size_t)j]] = j;
 
@@ -327,6 +343,8 @@ void dpdlp_params_default(dpdlp_params *p)
     p->fp32_stall_checks = 64;
     p->gather_slices = -1;
     p->use_graphs = 1;
+    p->perm_order = 0;
+    p->fp32_diverge = 10.0;
 }
 
 const char *dpdlp_status_string(int32_t s)

@@ -29,8 +29,14 @@ void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &i
                   int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out);
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
-constexpr int kTileNnzMax = 2048;    // products staged in LDS per tile
-constexpr int kMaxSegs = 1024;       // segments per tile
+#ifndef DPDLP_TILE_NNZ_MAX
+#define DPDLP_TILE_NNZ_MAX 2048
+#endif
+#ifndef DPDLP_TILE_SEGS_MAX
+#define DPDLP_TILE_SEGS_MAX 1024
+#endif
+constexpr int kTileNnzMax = DPDLP_TILE_NNZ_MAX;   // products staged in LDS per tile
+constexpr int kMaxSegs = DPDLP_TILE_SEGS_MAX;     // segments per tile
 
 void set_error(const std::string &msg);
 
@@ -64,6 +70,6 @@ void build_tiles(const int32_t *seg_ptr, int32_t nseg, int32_t tile_nnz,
                  std::vector<Tile> &out);
 // Permute rows/columns of a host CSR LP and build the CSC copy.
 void permute_and_transpose(const dpdlp_csr_lp *lp, int32_t block, uint64_t seed,
-                           HostMatrix &H);
+                           int32_t order, HostMatrix &H);
 
 }  // namespace dpdlp

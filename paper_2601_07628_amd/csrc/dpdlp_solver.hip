@@ -357,6 +357,7 @@ struct dpdlp_problem {
     // iterate and data, FP32 (mixed precision)
     float *x32 = nullptr, *y32 = nullptr, *xbar32 = nullptr, *xa32 = nullptr, *ya32 = nullptr;
     float *c32 = nullptr, *clo32 = nullptr, *chi32 = nullptr, *vlo32 = nullptr, *vhi32 = nullptr;
+    double *xbest = nullptr, *ybest = nullptr;  // T(z) of the FP32 phase's best check
     // scratch
     double *tmp_m = nullptr, *tmp_n = nullptr, *tmp_m2 = nullptr, *tmp_n2 = nullptr;
     double *scal = nullptr;         // device scalars: [0] lam, [4..7] norms
@@ -373,6 +374,7 @@ struct dpdlp_problem {
     int32_t status = DPDLP_RUNNING;
     bool in_fp32 = false;
     double fp32_ref_kkt = INFINITY;
+    double fp32_best_kkt = INFINITY, fp32_best_omega = 1.0;
     int fp32_stall = 0;
     bool initialized = false;
     double setup_seconds = 0, solve_seconds = 0;
@@ -781,7 +783,7 @@ static int check_buffers(dpdlp_problem *P)
         }
     if (P->prm.precision == DPDLP_FP32_MIXED) {
         const void *r32[] = {P->v32, P->vt32, P->x32, P->y32, P->xbar32, P->xa32, P->ya32,
-                             P->c32, P->clo32, P->chi32, P->vlo32, P->vhi32};
+                             P->c32, P->clo32, P->chi32, P->vlo32, P->vhi32, P->xbest, P->ybest};
         for (const void *p : r32)
             if (!p) { set_error("internal: FP32 buffer not allocated"); return DPDLP_E_HIP; }
         for (const SlicedSet *ss : {&P->sr, &P->sc})
@@ -874,6 +876,10 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     }
     if (P->prm.tile_nnz > kTileNnzMax) P->prm.tile_nnz = kTileNnzMax;
     if (P->prm.check_period < 1) P->prm.check_period = 1;
+    if (P->prm.perm_order < 0 || P->prm.perm_order > 3) {
+        set_error("perm_order must be 0..3 (bit 0: rows hot-first, bit 1: columns hot-first)");
+        return DPDLP_E_INVALID_ARG;
+    }
     P->s = (hipStream_t)stream;
     P->m = lp.m; P->n = lp.n; P->nnz = lp.row_ptr[lp.m];
     const int32_t m = P->m, n = P->n;
@@ -881,7 +887,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
 
     // A1 + A0: block-wise random permutation, then the CSC copy (host).
     HostMatrix H;
-    permute_and_transpose(&lp, P->prm.perm_block, P->prm.perm_seed, H);
+    permute_and_transpose(&lp, P->prm.perm_block, P->prm.perm_seed, P->prm.perm_order, H);
     P->h_perm_row = H.perm_row;
     P->h_perm_col = H.perm_col;
 
@@ -903,7 +909,9 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     // XCD-sliced fused steps: S > 0 slices both steps; S < 0 (automatic)
     // slices a step with S = 8 when its gathered vector exceeds one XCD's L2
     // (4 MB) and its partial sums (8 per segment) cost under a third of its
-    // matrix stream (12 bytes per nonzero).
+    // matrix stream (12 bytes per nonzero); never when the gathered dimension
+    // is in hot-first order (equal index ranges would put most nonzeros in
+    // one slice, and the order itself gives the cache locality).
     int Sd = 0, Sp = 0;                 // dual (CSR, gathers x), primal (CSC, gathers y)
     if (P->prm.gather_slices > 0) {
         if (P->prm.gather_slices % 8 != 0 || P->prm.gather_slices > 64) {
@@ -913,8 +921,9 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         Sd = Sp = P->prm.gather_slices;
     } else if (P->prm.gather_slices < 0) {
         const double mat = 12.0 * (double)nnz;
-        if (8.0 * n > 4.0 * (1 << 20) && 8.0 * 8.0 * m < mat / 3.0) Sd = 8;
-        if (8.0 * m > 4.0 * (1 << 20) && 8.0 * 8.0 * n < mat / 3.0) Sp = 8;
+        const bool hot_rows = P->prm.perm_order & 1, hot_cols = P->prm.perm_order & 2;
+        if (!hot_cols && 8.0 * n > 4.0 * (1 << 20) && 8.0 * 8.0 * m < mat / 3.0) Sd = 8;
+        if (!hot_rows && 8.0 * m > 4.0 * (1 << 20) && 8.0 * 8.0 * n < mat / 3.0) Sp = 8;
     }
     if (Sd) CHK(build_sliced(P, H.rp, H.ci, m, n, Sd, P->sr));     // dual: gathers xbar
     if (Sp) CHK(build_sliced(P, H.cp, H.ri, n, m, Sp, P->sc));     // primal: gathers y
@@ -1013,6 +1022,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         for (auto pp : nf) CHK(dalloc(P, pp, (size_t)n));
         float **mf[] = {&P->y32, &P->ya32, &P->clo32, &P->chi32};
         for (auto pp : mf) CHK(dalloc(P, pp, (size_t)m));
+        CHK(dalloc(P, &P->xbest, (size_t)n)); CHK(dalloc(P, &P->ybest, (size_t)m));
         auto cv = [&](const double *a, float *b, int64_t k) {
             if (k) hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(k)), dim3(kBlock), 0, P->s, a, b, k);
         };
@@ -1069,6 +1079,7 @@ static int init_impl(dpdlp_problem *P, const double *x0, const double *y0, int m
     P->k = 0; P->t = 0; P->fp32_iters = 0;
     P->status = DPDLP_RUNNING;
     P->fp32_ref_kkt = INFINITY;
+    P->fp32_best_kkt = INFINITY;
     P->fp32_stall = 0;
     P->solve_seconds = 0;
     P->log.clear();
@@ -1080,10 +1091,16 @@ static int init_impl(dpdlp_problem *P, const double *x0, const double *y0, int m
     return DPDLP_OK;
 }
 
-// FP32 -> FP64 switch: continue in FP64 from T(z) of the last check, as a
-// fresh epoch anchored there (no primal-weight update).
-static int switch_to_fp64(dpdlp_problem *P)
+// FP32 -> FP64 switch: continue in FP64 as a fresh epoch anchored at T(z)
+// of the last check, or, after a divergence, at the FP32 phase's best check
+// point (lowest KKT error) with the primal weight that produced it.
+static int switch_to_fp64(dpdlp_problem *P, bool from_best)
 {
+    if (from_best) {
+        HIPCHK(hipMemcpyAsync(P->xh, P->xbest, sizeof(double) * P->n, hipMemcpyDeviceToDevice, P->s));
+        HIPCHK(hipMemcpyAsync(P->yh, P->ybest, sizeof(double) * P->m, hipMemcpyDeviceToDevice, P->s));
+        P->omega = P->fp32_best_omega;
+    }
     hipLaunchKernelGGL(k_restart<double>, dim3(nblk(std::max(P->m, P->n))), dim3(kBlock), 0, P->s,
                        P->m, P->n, P->xh, P->yh, P->x, P->xa, P->y, P->ya);
     P->in_fp32 = false;
@@ -1138,6 +1155,13 @@ static int iterate_impl(dpdlp_problem *P, int64_t n_iters)
         rec.omega = P->omega; rec.restart = C.restart;
         P->log.push_back(rec);
         if (C.numerical) { P->status = DPDLP_NUMERICAL; P->t++; break; }
+        const double kkt = std::max(C.r_primal, std::max(C.r_dual, C.r_gap));
+        if (P->in_fp32 && kkt < P->fp32_best_kkt) {    // keep the FP32 phase's best point
+            P->fp32_best_kkt = kkt;
+            P->fp32_best_omega = P->omega;
+            HIPCHK(hipMemcpyAsync(P->xbest, P->xh, sizeof(double) * P->n, hipMemcpyDeviceToDevice, P->s));
+            HIPCHK(hipMemcpyAsync(P->ybest, P->yh, sizeof(double) * P->m, hipMemcpyDeviceToDevice, P->s));
+        }
         if (C.converged) {           // the KKT is evaluated in FP64 in both precisions
             P->status = DPDLP_CONVERGED;
             P->t++;
@@ -1157,15 +1181,17 @@ static int iterate_impl(dpdlp_problem *P, int64_t n_iters)
         }
         P->t++;
         if (P->in_fp32) {            // FP32 -> FP64 switch rule
-            const double kkt = std::max(C.r_primal, std::max(C.r_dual, C.r_gap));
-            bool sw = kkt <= P->prm.fp32_switch_tol;
+            // tolerance reached, divergence (KKT far above the phase's best:
+            // FP32 rounding amplified by a small primal weight), or stall
+            const bool diverged = P->prm.fp32_diverge > 0 && kkt > P->prm.fp32_diverge * P->fp32_best_kkt;
+            bool sw = kkt <= P->prm.fp32_switch_tol || diverged;
             if (kkt <= 0.5 * P->fp32_ref_kkt || P->fp32_ref_kkt == INFINITY) {
                 P->fp32_ref_kkt = kkt;
                 P->fp32_stall = 0;
             } else if (++P->fp32_stall >= P->prm.fp32_stall_checks) {
                 sw = true;
             }
-            if (sw) CHK(switch_to_fp64(P));
+            if (sw) CHK(switch_to_fp64(P, diverged));
         }
         if (P->prm.time_limit > 0) {
             double el = P->solve_seconds +
@@ -1329,6 +1355,7 @@ int dpdlp_set_params(dpdlp_problem *P, const dpdlp_params *q)
     p.beta_suf = q->beta_suf; p.beta_nec = q->beta_nec; p.beta_art = q->beta_art;
     p.kp = q->kp; p.ki = q->ki; p.kd = q->kd; p.xcd_remap = q->xcd_remap;
     p.fp32_switch_tol = q->fp32_switch_tol; p.fp32_stall_checks = q->fp32_stall_checks;
+    p.fp32_diverge = q->fp32_diverge;
     p.use_graphs = q->use_graphs;
     drop_graphs(P);                 // gamma is a captured kernel argument
     return DPDLP_OK;

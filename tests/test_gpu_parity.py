@@ -187,10 +187,27 @@ def test_sliced_fp32_mixed_and_determinism(D, O):
     assert abs(r1["obj_primal"] - o["obj_p"]) <= 1e-7 * (1 + abs(o["obj_p"]))
 
 
-@pytest.mark.parametrize("remap,block", [(0, 256), (1, 0)])
-def test_iterate_parity_launch_variants(D, O, remap, block):
-    """XCD remap off / permutation off change only the summation order."""
-    fixed_run(D, O, lpgen.config0(), 500, gpu_kw=dict(xcd_remap=remap, perm_block=block))
+@pytest.mark.parametrize("remap,block,order", [(0, 256, 0), (1, 0, 0), (1, 256, 1), (1, 256, 2), (0, 0, 3)])
+def test_iterate_parity_launch_variants(D, O, remap, block, order):
+    """XCD remap off, permutation off and the hot-first order change only the
+    summation order."""
+    fixed_run(D, O, lpgen.config0(), 500,
+              gpu_kw=dict(xcd_remap=remap, perm_block=block, perm_order=order))
+
+
+@pytest.mark.parametrize("order,slices", [(1, -1), (2, -1), (3, -1), (3, 8)])
+def test_hot_first_order_skewed_lp(D, O, order, slices):
+    """Hot-first order on a Zipf-degree LP with heavy rows (config-1 shape at
+    1/40 scale): the most frequent rows and columns move to the front, some
+    columns split over tiles; with S = 8 slices the slices are unequal in
+    nonzeros.  Iterates and restart log match the oracle."""
+    lp = lpgen.huge_share_lp(50000, 100000, seed=11)
+    fixed_run(D, O, lp, 200, gpu_kw=dict(perm_order=order, gather_slices=slices))
+
+
+def test_perm_order_rejects_unknown(D):
+    with pytest.raises(RuntimeError, match="perm_order"):
+        D.Problem(lpgen.config0(), gpu_params(D, perm_order=4))
 
 
 def test_split_segments_long_row_and_column(D, O):
@@ -285,6 +302,36 @@ def test_fp32_mixed_reaches_1e8(D, O):
     assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= 1e-8
     assert r["fp32_iters"] > 0
     assert abs(r["obj_primal"] - o["obj_p"]) <= 1e-7 * (1 + abs(o["obj_p"]))
+
+
+def test_fp32_divergence_switches_to_fp64_from_best_point(D, O):
+    """On config 4 the FP32 phase stalls near KKT 1e-4: the primal weight
+    falls, the primal step grows, and FP32 rounding of c - A^T y grows with
+    it.  The switch rule (KKT 10x above the phase's best) hands over to FP64
+    at the best check point, so the solve to 1e-4 takes at most twice the
+    FP64 iterations and reaches the oracle's objective."""
+    lp = lpgen.config4()
+    r64 = D.Problem(lp, gpu_params(D, eps=1e-4)).solve()
+    G = D.Problem(lp, gpu_params(D, eps=1e-4, precision=D.FP32_MIXED, fp32_switch_tol=0.0))
+    r = G.solve()
+    assert r["status"] == 1 and r64["status"] == 1
+    assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= 1e-4
+    assert r["iters"] <= 2 * r64["iters"], (r["iters"], r64["iters"])
+    kkt = lambda e: max(e["r_primal"], e["r_dual"], e["r_gap"])
+    lg = G.log()
+    fp32_checks = [e for e in lg if e["t"] < r["fp32_iters"]]
+    best = [min(kkt(e) for e in fp32_checks[:i + 1]) for i in range(len(fp32_checks))]
+    # the switch came from the divergence rule: the last FP32 check is 10x
+    # above the best before it, and no earlier one is
+    assert r["fp32_iters"] < r["iters"]
+    assert kkt(fp32_checks[-1]) > 10 * best[-2]
+    for i in range(1, len(fp32_checks) - 1):
+        assert kkt(fp32_checks[i]) <= 10 * best[i - 1], i
+    # FP64 resumed at the best point: its first check is near that KKT
+    first64 = next(e for e in lg if e["t"] >= r["fp32_iters"])
+    assert kkt(first64) <= 10 * best[-2]
+    o = O.Problem(lp, O.Params(eps=1e-4)).solve()
+    assert abs(r["obj_primal"] - o["obj_p"]) <= 1e-3 * (1 + abs(o["obj_p"]))
 
 
 # ---- determinism, checkpoint / resume ------------------------------------------------
