@@ -109,8 +109,9 @@ typedef struct dpdlp_params {
                               /* slice order (the 2-D partition of Sec. 3.1  */
                               /* across the 8 XCDs).  Automatic slices a step */
                               /* (S = 8) when its gathered vector exceeds 4 MB */
-                              /* and its 8 partials per segment cost under a  */
-                              /* third of its 12 bytes per nonzero.           */
+                              /* and its partial sums, one per (segment,      */
+                              /* slice) with nonzeros at 20 bytes each, cost  */
+                              /* less than its 12 bytes per nonzero.          */
     int32_t use_graphs;       /* 1: replay the check_period - 1 iterations    */
                               /* between two checks as one HIP graph (off    */
                               /* while dpdlp_profile_enable is on)           */

@@ -160,6 +160,20 @@ void build_tiles(const int32_t *ptr, int32_t nseg, int32_t tile_nnz,
     }
 }
 
+int64_t count_compact(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                      int32_t nseg, int32_t nidx, int32_t S)
+{
+    const int32_t size = (nidx + S - 1) / S;
+    std::vector<int32_t> last((size_t)S, -1);
+    int64_t G = 0;
+    for (int32_t g = 0; g < nseg; ++g)
+        for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
+            const int32_t s = idx[(size_t)p] / size;
+            if (last[(size_t)s] != g) { last[(size_t)s] = g; ++G; }
+        }
+    return G;
+}
+
 void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
                   int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out)
 {
@@ -167,34 +181,72 @@ void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &i
     out.size = (nidx + S - 1) / S;
     const int64_t nnz = ptr[(size_t)nseg];
     // count per (slice, segment)
-    std::vector<int64_t> cnt((size_t)S * (size_t)(nseg + 1), 0);
+    std::vector<int32_t> cnt((size_t)S * (size_t)nseg, 0);
     for (int32_t g = 0; g < nseg; ++g)
         for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p)
-            cnt[(size_t)(idx[(size_t)p] / out.size) * (size_t)(nseg + 1) + (size_t)g]++;
-    out.ptr.assign((size_t)S * (size_t)(nseg + 1), 0);
-    int64_t run = 0;
+            cnt[(size_t)(idx[(size_t)p] / out.size) * (size_t)nseg + (size_t)g]++;
+    // compact segments: slice-major, increasing segment within a slice
+    const int32_t planes = S / 8;
+    const int32_t nblk = (nseg + kBlock - 1) / kBlock;
+    out.seg_base.assign((size_t)S + 1, 0);
+    out.mask.assign((size_t)planes * (size_t)nseg, 0);
+    out.cbase.assign((size_t)nblk * (size_t)S, 0);
+    int64_t G = 0;
     for (int32_t s = 0; s < S; ++s) {
-        for (int32_t g = 0; g <= nseg; ++g) {
-            out.ptr[(size_t)s * (nseg + 1) + g] = (int32_t)run;
-            if (g < nseg) run += cnt[(size_t)s * (nseg + 1) + g];
+        out.seg_base[(size_t)s] = (int32_t)G;
+        const int32_t *c = cnt.data() + (size_t)s * nseg;
+        for (int32_t g = 0; g < nseg; ++g) {
+            if (g % kBlock == 0) out.cbase[(size_t)(g / kBlock) * S + s] = (int32_t)G;
+            if (c[g] > 0) {
+                out.mask[(size_t)(s / 8) * nseg + g] |= (uint8_t)(1u << (s % 8));
+                ++G;
+            }
         }
     }
+    out.seg_base[(size_t)S] = (int32_t)G;
+    out.G = G;
+    out.ptr.assign((size_t)G + 1, 0);
+    {
+        int64_t run = 0, q = 0;
+        for (int32_t s = 0; s < S; ++s) {
+            const int32_t *c = cnt.data() + (size_t)s * nseg;
+            for (int32_t g = 0; g < nseg; ++g)
+                if (c[g] > 0) { out.ptr[(size_t)q++] = (int32_t)run; run += c[g]; }
+        }
+        out.ptr[(size_t)G] = (int32_t)run;
+    }
+    // scatter the nonzeros: position of (s, g) is ptr[compact index]
     out.idx.resize((size_t)nnz);
     out.src.resize((size_t)nnz);
-    std::vector<int32_t> pos(out.ptr);
-    for (int32_t g = 0; g < nseg; ++g)
-        for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
-            const int32_t s = idx[(size_t)p] / out.size;
-            const int32_t q = pos[(size_t)s * (nseg + 1) + g]++;
-            out.idx[(size_t)q] = idx[(size_t)p];
-            out.src[(size_t)q] = p;
+    {
+        std::vector<int32_t> cur((size_t)S);
+        std::vector<int64_t> ci((size_t)S);
+        for (int32_t s = 0; s < S; ++s) ci[(size_t)s] = out.seg_base[(size_t)s];
+        for (int32_t g = 0; g < nseg; ++g) {
+            for (int32_t s = 0; s < S; ++s)
+                cur[(size_t)s] = cnt[(size_t)s * nseg + g] > 0 ? out.ptr[(size_t)ci[(size_t)s]] : -1;
+            for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
+                const int32_t s = idx[(size_t)p] / out.size;
+                const int32_t q = cur[(size_t)s]++;
+                out.idx[(size_t)q] = idx[(size_t)p];
+                out.src[(size_t)q] = p;
+            }
+            for (int32_t s = 0; s < S; ++s)
+                if (cnt[(size_t)s * nseg + g] > 0) ++ci[(size_t)s];
         }
+    }
+    // tiles per slice over its compact segments (global segment numbers)
     out.tiles.clear();
     std::vector<Tile> tt;
     for (int32_t s = 0; s < S; ++s) {
-        const int32_t *sp = out.ptr.data() + (size_t)s * (nseg + 1);
-        build_tiles(sp, nseg, tile_nnz, tt);
-        for (Tile t : tt) { t.slice = s; out.tiles.push_back(t); }
+        const int32_t b0 = out.seg_base[(size_t)s], ns = out.seg_base[(size_t)s + 1] - b0;
+        build_tiles(out.ptr.data() + b0, ns, tile_nnz, tt);
+        for (Tile t : tt) {
+            t.slice = s;
+            t.seg_begin += b0;
+            t.seg_end += b0;
+            out.tiles.push_back(t);
+        }
     }
 }
 

@@ -20,13 +20,25 @@ struct Tile {
 // present in every slice (possibly empty).  ptr has S*(nseg+1) entries with
 // global nonzero offsets into idx; src[q] is the position in the unsliced
 // format the value of sliced nonzero q comes from; tiles carry their slice.
+// The XCD-sliced form of one format in compact layout: slice s keeps only
+// the segments with a nonzero in its index range, numbered globally in
+// slice-major order ("compact segments", seg_base[s] .. seg_base[s+1]);
+// ptr has one entry per compact segment (+1) into idx/src.  mask holds, per
+// original segment, one bit per slice in S/8 byte planes (plane-major);
+// cbase[q * S + s] is the compact index of the first segment of slice s at
+// or after original segment q * kBlock.
 struct SlicedHost {
     int32_t S = 0, size = 0;
-    std::vector<int32_t> ptr, idx, src;
+    int64_t G = 0;
+    std::vector<int32_t> ptr, idx, src, seg_base, cbase;
+    std::vector<uint8_t> mask;
     std::vector<Tile> tiles;
 };
 void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
                   int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out);
+// Number of compact segments (segment, slice) with a nonzero, for S slices.
+int64_t count_compact(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                      int32_t nseg, int32_t nidx, int32_t S);
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 #ifndef DPDLP_TILE_NNZ_MAX

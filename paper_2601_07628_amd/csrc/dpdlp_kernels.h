@@ -412,35 +412,63 @@ struct PartialOp {
     int slice = 0;
     __device__ void resolve() {}
     const T *__restrict__ v;
-    T *__restrict__ partial;
+    T *__restrict__ partial;        // one value per compact segment
     double *partials;
-    int nseg;
     using Pre = NoPre;
     __device__ void value(MT a, int j, AT *o) const { o[0] = a * v[j]; }
     __device__ void prefetch(int, Pre &) const {}
-    __device__ void epilogue(int s, const AT *r, const Pre &, double *) const
+    __device__ void epilogue(int g, const AT *r, const Pre &, double *) const
     {
-        partial[(size_t)slice * nseg + s] = r[0];
+        partial[g] = r[0];
     }
 };
 
-// Adds the S slice partials of each segment in slice order and runs a fused
-// epilogue (PrimalOp / DualOp) on the sum; one thread per segment.
+// Adds the slice partials of each segment in slice order and runs a fused
+// epilogue (PrimalOp / DualOp) on the sum; one thread per segment.  The
+// partials are compact (only the slices where the segment has nonzeros):
+// the position of segment j's partial in slice s is cbase[block * S + s]
+// plus the number of segments of this block before j that have slice s,
+// counted with wave ballots over the mask bits.
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_combine(Op op0, int nseg, int S,
-                                                    const typename Op::AT *__restrict__ partial)
+                                                    const typename Op::AT *__restrict__ partial,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const int *__restrict__ cbase)
 {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= nseg) return;
+    using AT = typename Op::AT;
+    __shared__ int s_cnt[8][kBlock / 64];
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const bool in = j < nseg;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     Op op = op0;
     op.resolve();
     typename Op::Pre p;
-    op.prefetch(s, p);
-    typename Op::AT r[1];
-    r[0] = partial[s];
-    for (int q = 1; q < S; ++q) r[0] += partial[(size_t)q * nseg + s];
+    if (in) op.prefetch(j, p);
+    AT r[1];
+    r[0] = SumOp::template id<AT>();
+    const int *cb = cbase + (size_t)blockIdx.x * S;
+    for (int pl = 0; pl < S / 8; ++pl) {
+        const unsigned mb = in ? (unsigned)mask[(size_t)pl * nseg + j] : 0u;
+        unsigned long long bal[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bal[b] = __ballot((mb >> b) & 1u);
+            if (lane == 0) s_cnt[b][wave] = __popcll(bal[b]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            if ((mb >> b) & 1u) {
+                int off = cb[pl * 8 + b] + __popcll(bal[b] & below);
+                for (int w = 0; w < wave; ++w) off += s_cnt[b][w];
+                r[0] += partial[off];
+            }
+        }
+        __syncthreads();
+    }
     double acc[1];
-    op.epilogue(s, r, p, acc);
+    if (in) op.epilogue(j, r, p, acc);
 }
 
 // ---------------------------------------------------------------------------

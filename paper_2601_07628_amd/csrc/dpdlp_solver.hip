@@ -300,7 +300,7 @@ struct TileSet {
     int nsplit = 0;
     int *blk2tile = nullptr;        // sliced sets: workgroup -> tile (-1: idle)
     int grid = 0;                   // sliced sets: launch size
-    int seg_stride = 0;             // sliced sets: nseg + 1
+    int seg_stride = 0;             // per-slice pointer stride (0: one pointer array)
 };
 
 // One format cut into gather slices (the XCD-sliced form of a fused step).
@@ -310,6 +310,9 @@ struct SlicedSet {
     int *ptr = nullptr, *idx = nullptr, *src = nullptr;
     double *val = nullptr;
     float *val32 = nullptr;
+    uint8_t *mask = nullptr;        // per segment: slices with nonzeros (S/8 byte planes)
+    int *cbase = nullptr;           // per combine block and slice: first compact segment
+    int64_t G = 0;                  // compact segments (partial sums per pass)
 };
 
 // Gathers the (scaled) values of the unsliced format into the sliced order.
@@ -342,7 +345,7 @@ struct dpdlp_problem {
     float *v32 = nullptr, *vt32 = nullptr;
     TileSet tr, tc;
     SlicedSet sr, sc;               // XCD-sliced CSR (dual) and CSC (primal)
-    void *part_slices = nullptr;    // S x max(m, n) per-slice segment sums
+    void *part_slices = nullptr;    // compact per-slice segment sums
     void *carries = nullptr;
     double *part_r = nullptr, *part_c = nullptr;
     int *perm_row = nullptr, *perm_col = nullptr;
@@ -502,11 +505,11 @@ static void launch_primal(dpdlp_problem *P, const T *y, const T *c, const T *lo,
     op.write_hat = write_hat;
     if (P->sc.S > 0) {
         PartialOp<T> po;
-        po.v = y; po.partial = (T *)P->part_slices; po.partials = nullptr; po.nseg = P->n;
+        po.v = y; po.partial = (T *)P->part_slices; po.partials = nullptr;
         launch_tiles(P, po, P->sc.ts, P->sc.ptr, P->sc.idx,
                      (const T *)(sizeof(T) == 8 ? (const void *)P->sc.val : (const void *)P->sc.val32));
         hipLaunchKernelGGL(k_combine<PrimalOp<T>>, dim3(nblk(P->n)), dim3(kBlock), 0, P->s, op, P->n,
-                           P->sc.S, (const T *)P->part_slices);
+                           P->sc.S, (const T *)P->part_slices, P->sc.mask, P->sc.cbase);
         return;
     }
     launch_tiles(P, op, P->tc, P->cp, P->ri, vt);
@@ -529,11 +532,11 @@ static void launch_dual(dpdlp_problem *P, const T *xbar, const T *lo, const T *h
     op.write_hat = write_hat;
     if (P->sr.S > 0) {
         PartialOp<T> po;
-        po.v = xbar; po.partial = (T *)P->part_slices; po.partials = nullptr; po.nseg = P->m;
+        po.v = xbar; po.partial = (T *)P->part_slices; po.partials = nullptr;
         launch_tiles(P, po, P->sr.ts, P->sr.ptr, P->sr.idx,
                      (const T *)(sizeof(T) == 8 ? (const void *)P->sr.val : (const void *)P->sr.val32));
         hipLaunchKernelGGL(k_combine<DualOp<T>>, dim3(nblk(P->m)), dim3(kBlock), 0, P->s, op, P->m,
-                           P->sr.S, (const T *)P->part_slices);
+                           P->sr.S, (const T *)P->part_slices, P->sr.mask, P->sr.cbase);
         return;
     }
     launch_tiles(P, op, P->tr, P->rp, P->ci, v);
@@ -681,13 +684,18 @@ static int build_sliced(dpdlp_problem *P, const std::vector<int32_t> &ptr,
     CHK(dalloc(P, &ss.src, nnz));
     CHK(dalloc(P, &ss.val, nnz));
     CHK(upload(P, ss.ptr, sh.ptr.data(), sh.ptr.size() * sizeof(int32_t)));
+    ss.G = sh.G;
+    CHK(dalloc(P, &ss.mask, std::max<size_t>(sh.mask.size(), 1)));
+    CHK(dalloc(P, &ss.cbase, std::max<size_t>(sh.cbase.size(), 1)));
+    if (!sh.mask.empty()) CHK(upload(P, ss.mask, sh.mask.data(), sh.mask.size()));
+    if (!sh.cbase.empty()) CHK(upload(P, ss.cbase, sh.cbase.data(), sh.cbase.size() * sizeof(int32_t)));
     if (nnz) {
         CHK(upload(P, ss.idx, sh.idx.data(), nnz * sizeof(int32_t)));
         CHK(upload(P, ss.src, sh.src.data(), nnz * sizeof(int32_t)));
     }
     TileSet &ts = ss.ts;
     ts.n = (int)sh.tiles.size();
-    ts.seg_stride = nseg + 1;
+    ts.seg_stride = 0;              // compact segments are numbered globally
     std::vector<SplitSeg> sp;
     std::vector<std::vector<int>> per(8);
     for (int i = 0; i < ts.n; ++i) {
@@ -777,6 +785,7 @@ static int check_buffers(dpdlp_problem *P)
     }
     for (const SlicedSet *ss : {&P->sr, &P->sc})
         if (ss->S > 0 && (!ss->ptr || !ss->idx || !ss->val || !ss->ts.d || !ss->ts.blk2tile ||
+                          !ss->mask || !ss->cbase ||
                           !P->part_slices || (ss->ts.nsplit && !ss->ts.splits))) {
             set_error("internal: sliced buffers not allocated");
             return DPDLP_E_HIP;
@@ -908,8 +917,9 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     int ntmax = std::max(P->tr.n, P->tc.n);
     // XCD-sliced fused steps: S > 0 slices both steps; S < 0 (automatic)
     // slices a step with S = 8 when its gathered vector exceeds one XCD's L2
-    // (4 MB) and its partial sums (8 per segment) cost under a third of its
-    // matrix stream (12 bytes per nonzero); never when the gathered dimension
+    // (4 MB) and its compact partial sums (written and read, 8 + 8 bytes, plus
+    // a 4-byte pointer per compact segment) cost less than its matrix stream
+    // (12 bytes per nonzero); never when the gathered dimension
     // is in hot-first order (equal index ranges would put most nonzeros in
     // one slice, and the order itself gives the cache locality).
     int Sd = 0, Sp = 0;                 // dual (CSR, gathers x), primal (CSC, gathers y)
@@ -920,16 +930,16 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         }
         Sd = Sp = P->prm.gather_slices;
     } else if (P->prm.gather_slices < 0) {
-        const double mat = 12.0 * (double)nnz;
+        const double mat = 12.0 * (double)nnz, l2 = 4.0 * (1 << 20);
         const bool hot_rows = P->prm.perm_order & 1, hot_cols = P->prm.perm_order & 2;
-        if (!hot_cols && 8.0 * n > 4.0 * (1 << 20) && 8.0 * 8.0 * m < mat / 3.0) Sd = 8;
-        if (!hot_rows && 8.0 * m > 4.0 * (1 << 20) && 8.0 * 8.0 * n < mat / 3.0) Sp = 8;
+        if (!hot_cols && 8.0 * n > l2 && 20.0 * (double)count_compact(H.rp, H.ci, m, n, 8) < mat) Sd = 8;
+        if (!hot_rows && 8.0 * m > l2 && 20.0 * (double)count_compact(H.cp, H.ri, n, m, 8) < mat) Sp = 8;
     }
     if (Sd) CHK(build_sliced(P, H.rp, H.ci, m, n, Sd, P->sr));     // dual: gathers xbar
     if (Sp) CHK(build_sliced(P, H.cp, H.ri, n, m, Sp, P->sc));     // primal: gathers y
     if (Sd || Sp) {
         ntmax = std::max(ntmax, std::max(P->sr.ts.n, P->sc.ts.n));
-        const size_t ps = std::max((size_t)Sd * m, (size_t)Sp * n);
+        const size_t ps = (size_t)std::max<int64_t>(1, std::max(P->sr.G, P->sc.G));
         CHK(dalloc(P, (double **)&P->part_slices, ps));
     }
     // split-piece carries (2 right-hand sides) and per-tile partial sums
