@@ -81,9 +81,13 @@ typedef struct dpdlp_params {
     double eta;               /* > 0: fixed step; 0: eta_safety/sigma_max(A~)*/
     double omega0;            /* > 0: fixed initial primal weight; 0: ||c~||/||b~|| */
     double eta_safety;        /* 0.998                                       */
-    int32_t power_max_iters;  /* 5000                                        */
+    int32_t power_max_iters;  /* 5000: steps of each of the two sigma_max(A~) */
+                              /* estimates (Golub-Kahan-Lanczos bidiagonal- */
+                              /* ization from two seeded starts, the larger */
+                              /* kept)                                      */
     int32_t use_pc;           /* 1: one Pock-Chambolle pass after Ruiz       */
-    double power_tol;         /* 1e-6: relative change that stops the power iteration */
+    double power_tol;         /* 1e-6: an estimate stops when it grew by at  */
+                              /* most this (relative) over 8 steps          */
     double pc_alpha;          /* 1.0                                         */
     int32_t perm_block;       /* 256: block size of the block-wise random    */
                               /* permutation (Sec. 4.2); 0: no permutation   */
@@ -139,7 +143,7 @@ typedef struct dpdlp_result {
     double obj_primal, obj_dual;
     double omega, eta, sigma_max;
     double setup_seconds, solve_seconds;
-    int32_t power_iters, n_checks;
+    int32_t power_iters, n_checks;    /* Lanczos steps of the sigma_max estimate; checks */
 } dpdlp_result;
 
 /* Scalars of the iteration state, for checkpoint / resume and parity tests. */
@@ -166,8 +170,8 @@ void dpdlp_params_default(dpdlp_params *p);
 /* Ingest and prepare a problem on the current HIP device, on `stream`:
  * validate (host), block-wise random permutation of rows and columns
  * (Sec. 4.2), CSC build (App. E.3 keeps both formats), nonzero-aware
- * workgroup tiles (Sec. 4.3), Ruiz + Pock-Chambolle rescaling, the power
- * iteration for eta and the initial primal weight.  *out receives a handle
+ * workgroup tiles (Sec. 4.3), Ruiz + Pock-Chambolle rescaling, sigma_max(A~)
+ * by Lanczos bidiagonalization for eta, and the initial primal weight.  *out receives a handle
  * that owns every device buffer; free it with dpdlp_problem_destroy.
  * Errors: INVALID_ARG, BAD_CSR, BAD_BOUNDS, HIP, OOM.                     */
 int dpdlp_problem_create(const dpdlp_csr_lp *lp, const dpdlp_params *params,

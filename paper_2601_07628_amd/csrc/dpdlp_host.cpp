@@ -92,6 +92,66 @@ static inline uint64_t splitmix64(uint64_t &s)
     return z ^ (z >> 31);
 }
 
+// Runs f(t) for t = 0 .. n - 1 on n host threads.
+template <class F>
+static void run_threads(int n, F f)
+{
+    std::vector<std::thread> th;
+    for (int t = 1; t < n; ++t) th.emplace_back(f, t);
+    f(0);
+    for (auto &x : th) x.join();
+}
+
+static int host_threads()
+{
+    return (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+}
+
+double lanczos_start(int32_t n, uint64_t seed, double *w)
+{
+    uint64_t s = seed;
+    double ss = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+        w[j] = 2.0 * (double)(splitmix64(s) >> 11) * 0x1.0p-53 - 1.0;
+        ss += w[j] * w[j];
+    }
+    return std::sqrt(ss);
+}
+
+double bidiag_sigma_max(const double *alpha, const double *beta, int k)
+{
+    if (k <= 0) return 0.0;
+    // T = B^T B: T_ii = alpha_i^2 + beta_i^2 (beta_0 = 0), T_i,i+1 = alpha_i beta_i+1
+    std::vector<double> d((size_t)k), e((size_t)k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        const double b = i > 0 ? beta[i] : 0.0;
+        d[(size_t)i] = alpha[i] * alpha[i] + b * b;
+        if (i + 1 < k) e[(size_t)i] = alpha[i] * beta[i + 1];
+    }
+    double hi = 0.0;
+    for (int i = 0; i < k; ++i)
+        hi = std::max(hi, d[(size_t)i] + std::fabs(e[(size_t)i]) + (i > 0 ? std::fabs(e[(size_t)i - 1]) : 0.0));
+    if (!(hi > 0.0)) return 0.0;
+    // number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots)
+    auto below = [&](double x) {
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = 0; i < k; ++i) {
+            const double e2 = i > 0 ? e[(size_t)i - 1] * e[(size_t)i - 1] : 0.0;
+            q = d[(size_t)i] - x - (i > 0 ? e2 / q : 0.0);
+            if (q == 0.0) q = -1e-300 * hi;
+            if (q < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    double lo = 0.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) == k) hi = mid; else lo = mid;
+    }
+    return std::sqrt(0.5 * (lo + hi));
+}
+
 void block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t *perm)
 {
     if (block <= 0 || count <= block) {
@@ -160,82 +220,104 @@ void build_tiles(const int32_t *ptr, int32_t nseg, int32_t tile_nnz,
     }
 }
 
-int64_t count_compact(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+int64_t count_compact(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
                       int32_t nseg, int32_t nidx, int32_t S)
 {
     const int32_t size = (nidx + S - 1) / S;
-    std::vector<int32_t> last((size_t)S, -1);
+    const int nth = host_threads();
+    std::vector<int64_t> part((size_t)nth, 0);
+    run_threads(nth, [&](int t) {
+        const int32_t g0 = (int32_t)((int64_t)nseg * t / nth), g1 = (int32_t)((int64_t)nseg * (t + 1) / nth);
+        std::vector<int32_t> last((size_t)S, -1);
+        int64_t G = 0;
+        for (int32_t g = g0; g < g1; ++g)
+            for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
+                const int32_t s = idx[(size_t)p] / size;
+                if (last[(size_t)s] != g) { last[(size_t)s] = g; ++G; }
+            }
+        part[(size_t)t] = G;
+    });
     int64_t G = 0;
-    for (int32_t g = 0; g < nseg; ++g)
-        for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
-            const int32_t s = idx[(size_t)p] / size;
-            if (last[(size_t)s] != g) { last[(size_t)s] = g; ++G; }
-        }
+    for (int64_t v : part) G += v;
     return G;
 }
 
-void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
                   int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out)
 {
     out.S = S;
     out.size = (nidx + S - 1) / S;
+    const int32_t size = out.size;
     const int64_t nnz = ptr[(size_t)nseg];
-    // count per (slice, segment)
-    std::vector<int32_t> cnt((size_t)S * (size_t)nseg, 0);
-    for (int32_t g = 0; g < nseg; ++g)
-        for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p)
-            cnt[(size_t)(idx[(size_t)p] / out.size) * (size_t)nseg + (size_t)g]++;
-    // compact segments: slice-major, increasing segment within a slice
     const int32_t planes = S / 8;
     const int32_t nblk = (nseg + kBlock - 1) / kBlock;
-    out.seg_base.assign((size_t)S + 1, 0);
-    out.mask.assign((size_t)planes * (size_t)nseg, 0);
-    out.cbase.assign((size_t)nblk * (size_t)S, 0);
-    int64_t G = 0;
-    for (int32_t s = 0; s < S; ++s) {
-        out.seg_base[(size_t)s] = (int32_t)G;
-        const int32_t *c = cnt.data() + (size_t)s * nseg;
-        for (int32_t g = 0; g < nseg; ++g) {
-            if (g % kBlock == 0) out.cbase[(size_t)(g / kBlock) * S + s] = (int32_t)G;
-            if (c[g] > 0) {
-                out.mask[(size_t)(s / 8) * nseg + g] |= (uint8_t)(1u << (s % 8));
-                ++G;
+    const int nth = std::min(S, host_threads());
+    // 1. per (slice, segment) counts; slice s is counted by thread s % nth
+    hvec<int32_t> cnt((size_t)S * (size_t)nseg);      // every entry written below
+    std::vector<int64_t> gs((size_t)S, 0), zs((size_t)S, 0);
+    run_threads(nth, [&](int t) {
+        for (int32_t s = t; s < S; s += nth) {
+            const int32_t lo = s * size, hi = std::min(nidx, lo + size);
+            int32_t *c = cnt.data() + (size_t)s * nseg;
+            int64_t G = 0, Z = 0;
+            for (int32_t g = 0; g < nseg; ++g) {
+                int32_t k = 0;
+                for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p)
+                    k += (idx[(size_t)p] >= lo && idx[(size_t)p] < hi);
+                c[g] = k;
+                G += k > 0;
+                Z += k;
             }
+            gs[(size_t)s] = G;
+            zs[(size_t)s] = Z;
         }
+    });
+    // 2. compact numbering: slice-major, increasing segment within a slice
+    out.seg_base.assign((size_t)S + 1, 0);
+    std::vector<int64_t> nz_base((size_t)S + 1, 0);
+    for (int32_t s = 0; s < S; ++s) {
+        out.seg_base[(size_t)s + 1] = out.seg_base[(size_t)s] + (int32_t)gs[(size_t)s];
+        nz_base[(size_t)s + 1] = nz_base[(size_t)s] + zs[(size_t)s];
     }
-    out.seg_base[(size_t)S] = (int32_t)G;
+    const int64_t G = out.seg_base[(size_t)S];
     out.G = G;
-    out.ptr.assign((size_t)G + 1, 0);
-    {
-        int64_t run = 0, q = 0;
-        for (int32_t s = 0; s < S; ++s) {
-            const int32_t *c = cnt.data() + (size_t)s * nseg;
-            for (int32_t g = 0; g < nseg; ++g)
-                if (c[g] > 0) { out.ptr[(size_t)q++] = (int32_t)run; run += c[g]; }
-        }
-        out.ptr[(size_t)G] = (int32_t)run;
-    }
-    // scatter the nonzeros: position of (s, g) is ptr[compact index]
+    out.ptr.resize((size_t)G + 1);          // every entry written below
+    out.ptr[(size_t)G] = (int32_t)nnz;
+    out.cbase.assign((size_t)nblk * (size_t)S, 0);
     out.idx.resize((size_t)nnz);
     out.src.resize((size_t)nnz);
-    {
-        std::vector<int32_t> cur((size_t)S);
-        std::vector<int64_t> ci((size_t)S);
-        for (int32_t s = 0; s < S; ++s) ci[(size_t)s] = out.seg_base[(size_t)s];
-        for (int32_t g = 0; g < nseg; ++g) {
-            for (int32_t s = 0; s < S; ++s)
-                cur[(size_t)s] = cnt[(size_t)s * nseg + g] > 0 ? out.ptr[(size_t)ci[(size_t)s]] : -1;
-            for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
-                const int32_t s = idx[(size_t)p] / out.size;
-                const int32_t q = cur[(size_t)s]++;
-                out.idx[(size_t)q] = idx[(size_t)p];
-                out.src[(size_t)q] = p;
+    run_threads(nth, [&](int t) {
+        for (int32_t s = t; s < S; s += nth) {
+            const int32_t lo = s * size, hi = std::min(nidx, lo + size);
+            const int32_t *c = cnt.data() + (size_t)s * nseg;
+            int64_t q = out.seg_base[(size_t)s], pos = nz_base[(size_t)s];
+            for (int32_t g = 0; g < nseg; ++g) {
+                if (g % kBlock == 0) out.cbase[(size_t)(g / kBlock) * S + s] = (int32_t)q;
+                if (c[g] == 0) continue;
+                out.ptr[(size_t)q++] = (int32_t)pos;
+                for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
+                    const int32_t j = idx[(size_t)p];
+                    if (j < lo || j >= hi) continue;
+                    out.idx[(size_t)pos] = j;
+                    out.src[(size_t)pos] = p;
+                    ++pos;
+                }
             }
-            for (int32_t s = 0; s < S; ++s)
-                if (cnt[(size_t)s * nseg + g] > 0) ++ci[(size_t)s];
         }
-    }
-    // tiles per slice over its compact segments (global segment numbers)
+    });
+    // 3. slice masks, S / 8 byte planes
+    out.mask.assign((size_t)planes * (size_t)nseg, 0);
+    run_threads(host_threads(), [&](int t) {
+        const int nt = host_threads();
+        const int32_t g0 = (int32_t)((int64_t)nseg * t / nt), g1 = (int32_t)((int64_t)nseg * (t + 1) / nt);
+        for (int32_t s = 0; s < S; ++s) {
+            const int32_t *c = cnt.data() + (size_t)s * nseg;
+            uint8_t *mk = out.mask.data() + (size_t)(s / 8) * nseg;
+            for (int32_t g = g0; g < g1; ++g)
+                if (c[g] > 0) mk[g] |= (uint8_t)(1u << (s % 8));
+        }
+    });
+    // 4. tiles per slice over its compact segments (global segment numbers)
     out.tiles.clear();
     std::vector<Tile> tt;
     for (int32_t s = 0; s < S; ++s) {
@@ -307,19 +389,38 @@ void permute_and_transpose(const dpdlp_csr_lp *lp, int32_t block, uint64_t seed,
     }
     for (auto &t : th) t.join();
 
-    // CSC by counting, prefix sum and a stable scatter (row order kept).
+    // CSC by counting, prefix sum and a stable scatter (row order kept);
+    // thread t owns a range of columns and scans all rows in order.
     H.cp.assign((size_t)n + 1, 0);
-    for (int64_t p = 0; p < H.nnz; ++p) H.cp[(size_t)H.ci[(size_t)p] + 1]++;
+    const int nct = host_threads();
+    auto crange = [&](int t, int32_t &c0, int32_t &c1) {
+        c0 = (int32_t)((int64_t)n * t / nct);
+        c1 = (int32_t)((int64_t)n * (t + 1) / nct);
+    };
+    run_threads(nct, [&](int t) {
+        int32_t c0, c1;
+        crange(t, c0, c1);
+        for (int64_t p = 0; p < H.nnz; ++p) {
+            const int32_t j = H.ci[(size_t)p];
+            if (j >= c0 && j < c1) H.cp[(size_t)j + 1]++;
+        }
+    });
     for (int32_t j = 0; j < n; ++j) H.cp[(size_t)j + 1] += H.cp[(size_t)j];
     std::vector<int32_t> next(H.cp.begin(), H.cp.end() - 1);
     H.ri.resize((size_t)H.nnz);
     H.vt.resize((size_t)H.nnz);
-    for (int32_t i = 0; i < m; ++i)
-        for (int32_t p = H.rp[(size_t)i]; p < H.rp[(size_t)i + 1]; ++p) {
-            int32_t q = next[(size_t)H.ci[(size_t)p]]++;
-            H.ri[(size_t)q] = i;
-            H.vt[(size_t)q] = H.v[(size_t)p];
-        }
+    run_threads(nct, [&](int t) {
+        int32_t c0, c1;
+        crange(t, c0, c1);
+        for (int32_t i = 0; i < m; ++i)
+            for (int32_t p = H.rp[(size_t)i]; p < H.rp[(size_t)i + 1]; ++p) {
+                const int32_t j = H.ci[(size_t)p];
+                if (j < c0 || j >= c1) continue;
+                const int32_t q = next[(size_t)j]++;
+                H.ri[(size_t)q] = i;
+                H.vt[(size_t)q] = H.v[(size_t)p];
+            }
+    });
 }
 
 }  // namespace dpdlp

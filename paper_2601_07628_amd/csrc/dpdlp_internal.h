@@ -2,7 +2,10 @@
 // and the device solver (dpdlp_solver.hip).
 #pragma once
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/dpdlp.h"
@@ -15,29 +18,43 @@ struct Tile {
     int32_t width_log2, piece, npieces, slice;   // slice: gather slice (sliced sets)
 };
 
-// A matrix format cut along its gathered dimension into S slices: slice s
-// holds the nonzeros whose index lies in [s*size, (s+1)*size), every segment
-// present in every slice (possibly empty).  ptr has S*(nseg+1) entries with
-// global nonzero offsets into idx; src[q] is the position in the unsliced
-// format the value of sliced nonzero q comes from; tiles carry their slice.
-// The XCD-sliced form of one format in compact layout: slice s keeps only
-// the segments with a nonzero in its index range, numbered globally in
-// slice-major order ("compact segments", seg_base[s] .. seg_base[s+1]);
-// ptr has one entry per compact segment (+1) into idx/src.  mask holds, per
+// Host arrays of matrix size: resize() leaves the elements uninitialised,
+// so that the threads that fill them also take their first-touch page
+// faults (a zero-filling resize of 40M elements costs about a second).
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U> struct rebind { using other = NoInitAlloc<U>; };
+    NoInitAlloc() = default;
+    template <class U> NoInitAlloc(const NoInitAlloc<U> &) {}
+    template <class U, class... A> void construct(U *p, A &&...a)
+    {
+        if constexpr (sizeof...(A) == 0) ::new ((void *)p) U;
+        else ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T> using hvec = std::vector<T, NoInitAlloc<T>>;
+
+// The XCD-sliced form of one format (gathered dimension cut into S slices
+// of `size` indices) in compact layout: slice s keeps only the segments
+// with a nonzero in its index range, numbered globally in slice-major order
+// ("compact segments", seg_base[s] .. seg_base[s+1]); ptr has one entry per
+// compact segment (+1) into idx/src, and src[q] is the position in the
+// unsliced format that sliced nonzero q comes from.  mask holds, per
 // original segment, one bit per slice in S/8 byte planes (plane-major);
 // cbase[q * S + s] is the compact index of the first segment of slice s at
-// or after original segment q * kBlock.
+// or after original segment q * kBlock.  Tiles carry their slice.
 struct SlicedHost {
     int32_t S = 0, size = 0;
     int64_t G = 0;
-    std::vector<int32_t> ptr, idx, src, seg_base, cbase;
+    hvec<int32_t> ptr, idx, src;
+    std::vector<int32_t> seg_base, cbase;
     std::vector<uint8_t> mask;
     std::vector<Tile> tiles;
 };
-void slice_format(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
                   int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out);
 // Number of compact segments (segment, slice) with a nonzero, for S slices.
-int64_t count_compact(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+int64_t count_compact(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
                       int32_t nseg, int32_t nidx, int32_t S);
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
@@ -56,10 +73,10 @@ void set_error(const std::string &msg);
 struct HostMatrix {
     int32_t m = 0, n = 0;
     int64_t nnz = 0;
-    std::vector<int32_t> rp, ci;      // CSR (permuted)
-    std::vector<double> v;
-    std::vector<int32_t> cp, ri;      // CSC (permuted), row order kept
-    std::vector<double> vt;
+    hvec<int32_t> rp, ci;             // CSR (permuted)
+    hvec<double> v;
+    hvec<int32_t> cp, ri;             // CSC (permuted), row order kept
+    hvec<double> vt;
     std::vector<int32_t> perm_row, perm_col;   // perm[new] = old
 };
 
@@ -77,6 +94,13 @@ struct ProblemView {
 int problem_view(dpdlp_problem *P, ProblemView *out);
 
 int validate_host(const dpdlp_csr_lp *lp);
+// Start vector of the Golub-Kahan-Lanczos process: w[j] in [-1, 1) from a
+// splitmix64 stream; returns ||w||_2.
+double lanczos_start(int32_t n, uint64_t seed, double *w);
+// Largest singular value of the k x k upper bidiagonal matrix with diagonal
+// alpha[0..k-1] and superdiagonal beta[1..k-1] (beta[0] unused), from the
+// largest eigenvalue of B^T B by Sturm-sequence bisection.
+double bidiag_sigma_max(const double *alpha, const double *beta, int k);
 void block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t *perm);
 void build_tiles(const int32_t *seg_ptr, int32_t nseg, int32_t tile_nnz,
                  std::vector<Tile> &out);

@@ -586,6 +586,33 @@ struct SpmvOp {
     }
 };
 
+// One half-step of the Golub-Kahan-Lanczos bidiagonalization, with the
+// normalisations deferred to the scalars: out <- (A in) / nin - (nin / nprev)
+// out (first: no second term); per-tile partials of sum out^2.
+struct LanczosOp {
+    using MT = double; using AT = double; using R = SumOp;
+    static constexpr int NR = 1, NQ = 1;
+    int slice = 0;
+    __device__ void resolve() {}
+    const double *__restrict__ in;
+    double *__restrict__ out;
+    const double *nin;              // ||in|| (device scalar)
+    const double *nprev;            // norm of the previous out (device scalar)
+    int first;
+    double *partials;
+    __device__ void value(MT v, int j, AT *o) const { o[0] = v * in[j]; }
+    struct Pre { double o; };
+    __device__ void prefetch(int s, Pre &p) const { p.o = first ? 0.0 : out[s]; }
+    __device__ void epilogue(int s, const AT *r, const Pre &p, double *acc) const
+    {
+        const double a = *nin;
+        double v = r[0] / a;
+        if (!first) v -= (a / *nprev) * p.o;
+        out[s] = v;
+        acc[0] += v * v;
+    }
+};
+
 // Rescaling reductions: Ruiz (max |a|) and Pock-Chambolle (sum |a|^p);
 // epilogue writes the factor 1/sqrt(.) (1 for an empty / zero segment).
 struct AbsMaxOp {

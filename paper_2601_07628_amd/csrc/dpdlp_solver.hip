@@ -127,16 +127,42 @@ __global__ __launch_bounds__(kBlock) void k_norm_partials(int m, int n, const do
         for (int q = 0; q < 4; ++q) partials[(size_t)q * gridDim.x + blockIdx.x] = acc[q];
 }
 
-// Single-workgroup fixed-order sum of nq rows of partials[q * np + i].
+// Single-workgroup fixed-order sum of nq rows of partials[q * np + i]:
+// thread t adds i = t, t + kBlock, ... in that order, then a tree over the
+// threads.  The loads of U strided steps of every row are issued before
+// their adds (same order, more loads in flight).
 template <int NQMAX>
 __device__ void sum_partials(const double *partials, int np, int nq, double *out)
 {
     __shared__ double s[NQMAX][kBlock];
-    for (int q = 0; q < nq; ++q) {
-        double a = 0.0;
-        for (int i = threadIdx.x; i < np; i += kBlock) a += partials[(size_t)q * np + i];
-        s[q][threadIdx.x] = a;
+    constexpr int U = 8;
+    double a[NQMAX];
+#pragma unroll
+    for (int q = 0; q < NQMAX; ++q) a[q] = 0.0;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * kBlock < np; i += U * kBlock) {
+        double v[NQMAX][U];
+#pragma unroll
+        for (int q = 0; q < NQMAX; ++q)
+            if (q < nq) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[q][u] = partials[(size_t)q * np + i + u * kBlock];
+            }
+#pragma unroll
+        for (int q = 0; q < NQMAX; ++q)
+            if (q < nq) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) a[q] += v[q][u];
+            }
     }
+    for (; i < np; i += kBlock) {
+#pragma unroll
+        for (int q = 0; q < NQMAX; ++q)
+            if (q < nq) a[q] += partials[(size_t)q * np + i];
+    }
+#pragma unroll
+    for (int q = 0; q < NQMAX; ++q)
+        if (q < nq) s[q][threadIdx.x] = a[q];
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w)
@@ -154,16 +180,16 @@ __global__ __launch_bounds__(kBlock) void k_sum_rows(const double *partials, int
     sum_partials<8>(partials, np, nq, out);
 }
 
-// Power iteration: lam = ||w||, sig_hist[it] = sqrt(lam).
-__global__ __launch_bounds__(kBlock) void k_power_finish(const double *partials, int np,
-                                                         double *lam, double *sig_hist, int it)
+// Lanczos: *norm = sqrt(sum of the partials), also kept in hist[idx].
+__global__ __launch_bounds__(kBlock) void k_lanczos_norm(const double *partials, int np,
+                                                         double *norm, double *hist, int idx)
 {
     __shared__ double tot;
     sum_partials<1>(partials, np, 1, &tot);
     if (threadIdx.x == 0) {
         const double l = sqrt(tot);
-        *lam = l;
-        sig_hist[it] = sqrt(l);
+        *norm = l;
+        hist[idx] = l;
     }
 }
 
@@ -648,7 +674,7 @@ static int upload(dpdlp_problem *P, void *dst, const void *src, size_t bytes)
     return DPDLP_OK;
 }
 
-static int build_tileset(dpdlp_problem *P, const std::vector<int32_t> &ptr, int32_t nseg,
+static int build_tileset(dpdlp_problem *P, const hvec<int32_t> &ptr, int32_t nseg,
                          TileSet &ts, std::vector<Tile> &host_tiles)
 {
     build_tiles(ptr.data(), nseg, P->prm.tile_nnz, host_tiles);
@@ -671,8 +697,8 @@ static int build_tileset(dpdlp_problem *P, const std::vector<int32_t> &ptr, int3
 
 // Sliced copy of one format: tiles of slice s run on XCD s % 8 (workgroup b
 // runs on XCD b % 8), the slices of one XCD one after another.
-static int build_sliced(dpdlp_problem *P, const std::vector<int32_t> &ptr,
-                        const std::vector<int32_t> &idx, int32_t nseg, int32_t nidx, int S,
+static int build_sliced(dpdlp_problem *P, const hvec<int32_t> &ptr,
+                        const hvec<int32_t> &idx, int32_t nseg, int32_t nidx, int S,
                         SlicedSet &ss)
 {
     SlicedHost sh;
@@ -722,48 +748,83 @@ static int build_sliced(dpdlp_problem *P, const std::vector<int32_t> &ptr,
     return DPDLP_OK;
 }
 
-static int power_iteration(dpdlp_problem *P)
+// sigma_max(A~) by Golub-Kahan-Lanczos bidiagonalization from one seeded
+// start (no reorthogonalisation; the largest Ritz value converges from
+// below):
+//   z_k = A~ v_k - beta_k u_(k-1),     alpha_k = ||z_k||,   u_k = z_k / alpha_k
+//   w_k+1 = A~^T u_k - alpha_k v_k,    beta_k+1 = ||w_k+1||, v_k+1 = w_k+1 / beta_k+1
+// The estimate after k steps is sigma_max of the k x k upper bidiagonal
+// (alpha, beta).  It stops when the estimate grew by at most power_tol
+// (relative) over the last 8 steps (k >= 16), at a breakdown (exact), or
+// after max_steps steps.
+static int lanczos_sigma(dpdlp_problem *P, uint64_t seed, int max_steps, double *sigma, int *steps)
 {
-    // v0 = 1/sqrt(n) (stored as w with lam = 1); each step u = A~ (w / lam),
-    // w = A~^T u, lam = ||w||, sigma = sqrt(lam); stop at the first step whose
-    // relative change is <= power_tol.
-    const int maxit = std::max(1, P->prm.power_max_iters);
-    double *lam = P->scal;
-    hipLaunchKernelGGL(k_fill<double>, dim3(nblk(P->n)), dim3(kBlock), 0, P->s, P->tmp_n2,
-                       1.0 / std::sqrt((double)P->n), (int64_t)P->n);
-    hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(1), 0, P->s, lam, 1.0, (int64_t)1);
-    std::vector<double> hist((size_t)maxit + 1, 0.0);
-    int it_done = 0, stop = -1;
-    const int chunk = 32;
-    for (int it0 = 1; it0 <= maxit && stop < 0; it0 += chunk) {
-        const int it1 = std::min(maxit, it0 + chunk - 1);
-        for (int it = it0; it <= it1; ++it) {
-            SpmvOp a;
-            a.in = P->tmp_n2; a.div = lam; a.out = P->tmp_m; a.partials = P->part_r;
+    const int maxit = std::max(1, max_steps);
+    const int32_t n = P->n;
+    double *w = P->tmp_n2, *z = P->tmp_m;
+    double *beta = P->scal + 8, *alpha = P->scal + 9;
+    double *ha = P->sig_hist, *hb = P->sig_hist + (maxit + 2);
+    {
+        std::vector<double> w0((size_t)n);
+        const double b1 = lanczos_start(n, seed, w0.data());
+        CHK(upload(P, w, w0.data(), sizeof(double) * (size_t)n));
+        CHK(upload(P, beta, &b1, sizeof(double)));
+    }
+    std::vector<double> al((size_t)maxit + 2, 0.0), be((size_t)maxit + 2, 0.0);
+    std::vector<double> est((size_t)maxit + 2, 0.0);
+    int stop = -1, k_done = 0;
+    const int chunk = 16, window = 8;
+    for (int k0 = 1; k0 <= maxit && stop < 0; k0 += chunk) {
+        const int k1 = std::min(maxit, k0 + chunk - 1);
+        for (int k = k0; k <= k1; ++k) {
+            LanczosOp a;
+            a.in = w; a.out = z; a.nin = beta; a.nprev = alpha; a.first = k == 1;
+            a.partials = P->part_r;
             launch_tiles(P, a, P->tr, P->rp, P->ci, P->v);
-            SpmvOp b;
-            b.in = P->tmp_m; b.div = nullptr; b.out = P->tmp_n2; b.partials = P->part_c;
+            hipLaunchKernelGGL(k_lanczos_norm, dim3(1), dim3(kBlock), 0, P->s, P->part_r, P->tr.n,
+                               alpha, ha, k);
+            LanczosOp b;
+            b.in = z; b.out = w; b.nin = alpha; b.nprev = beta; b.first = 0;
+            b.partials = P->part_c;
             launch_tiles(P, b, P->tc, P->cp, P->ri, P->vt);
-            hipLaunchKernelGGL(k_power_finish, dim3(1), dim3(kBlock), 0, P->s, P->part_c,
-                               P->tc.n, lam, P->sig_hist, it);
+            hipLaunchKernelGGL(k_lanczos_norm, dim3(1), dim3(kBlock), 0, P->s, P->part_c, P->tc.n,
+                               beta, hb, k + 1);
         }
-        HIPCHK(hipMemcpyAsync(hist.data() + it0, P->sig_hist + it0,
-                              sizeof(double) * (size_t)(it1 - it0 + 1), hipMemcpyDeviceToHost,
-                              P->s));
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(al.data() + k0, ha + k0, sizeof(double) * (size_t)(k1 - k0 + 1),
+                              hipMemcpyDeviceToHost, P->s));
+        HIPCHK(hipMemcpyAsync(be.data() + k0 + 1, hb + k0 + 1, sizeof(double) * (size_t)(k1 - k0 + 1),
+                              hipMemcpyDeviceToHost, P->s));
         HIPCHK(hipStreamSynchronize(P->s));
-        for (int it = it0; it <= it1; ++it) {
-            it_done = it;
-            const double sg = hist[(size_t)it];
-            if (sg == 0.0) { stop = it; break; }
-            if (it > 1 && std::fabs(sg - hist[(size_t)it - 1]) <= P->prm.power_tol * sg) {
-                stop = it;
+        for (int k = k0; k <= k1; ++k) {
+            if (!(al[(size_t)k] > 0.0) || !std::isfinite(al[(size_t)k])) { stop = k - 1; break; }
+            est[(size_t)k] = bidiag_sigma_max(al.data() + 1, be.data() + 1, k);
+            k_done = k;
+            if (!(be[(size_t)k + 1] > 0.0)) { stop = k; break; }      // invariant subspace: exact
+            if (k >= 2 * window &&
+                est[(size_t)k] - est[(size_t)(k - window)] <= P->prm.power_tol * est[(size_t)k]) {
+                stop = k;
                 break;
             }
         }
     }
-    if (stop < 0) stop = it_done;
-    P->power_iters = stop;
-    P->sigma_max = hist[(size_t)stop];
+    if (stop < 0) stop = k_done;
+    *sigma = stop >= 1 ? est[(size_t)stop] : 0.0;
+    *steps = stop;
+    return DPDLP_OK;
+}
+
+// sigma_max(A~): the larger of two Lanczos estimates from independent
+// starts (a start nearly orthogonal to the top singular vector can settle
+// on the second singular value).
+static int power_iteration(dpdlp_problem *P)
+{
+    double s1 = 0, s2 = 0;
+    int k1 = 0, k2 = 0;
+    CHK(lanczos_sigma(P, P->prm.perm_seed ^ 0x5EED1A2Cull, P->prm.power_max_iters, &s1, &k1));
+    CHK(lanczos_sigma(P, P->prm.perm_seed ^ 0x7A11C0DEull, P->prm.power_max_iters, &s2, &k2));
+    P->sigma_max = std::max(s1, s2);
+    P->power_iters = k1 + k2;
     return DPDLP_OK;
 }
 
@@ -974,7 +1035,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
                        &P->tmp_m, &P->tmp_m2};
     for (auto pp : mvec) CHK(dalloc(P, pp, (size_t)m));
     CHK(dalloc(P, &P->scal, 16));
-    CHK(dalloc(P, &P->sig_hist, (size_t)std::max(1, P->prm.power_max_iters) + 2));
+    CHK(dalloc(P, &P->sig_hist, 2 * ((size_t)std::max(1, P->prm.power_max_iters) + 2)));
     CHK(dalloc(P, &P->ctl, 1));
     CHK(dalloc(P, &P->ctl_eval, 1));
     CHK(dalloc(P, &P->iterdev, 1));
