@@ -3,8 +3,10 @@
     python -m paper_2601_07628_amd.rocprof_summary trace  <kernel_stats.csv>
     python -m paper_2601_07628_amd.rocprof_summary traffic <fetch_counter.csv> <write_counter.csv> \
         --out profiles/traffic.json --workload c1
+    python -m paper_2601_07628_amd.rocprof_summary l2 <tcc_hit_miss_counter.csv>
 
-`trace` prints a per-kernel table (calls, mean/min/max duration).  `traffic`
+`trace` prints a per-kernel table (calls, mean/min/max duration); `l2`
+prints mean L2 (TCC) hits, misses and hit rate per dispatch of each kernel.  `traffic`
 turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs (KiB per dispatch)
 into HBM bytes per launch of the fused kernels.  The counters are calibrated
 by the 256 MiB device-to-device copy that ``bench.py --calib-copy`` runs first
@@ -157,11 +159,29 @@ def traffic(fetch_csv, write_csv, workload):
     return out
 
 
+def l2_table(path):
+    hits = read_counter(path, "TCC_HIT_sum")
+    miss = {d: v for d, _, v in read_counter(path, "TCC_MISS_sum")}
+    per = defaultdict(lambda: [0, 0.0, 0.0])
+    for d, name, h in hits:
+        e = per[short_name(name)]
+        e[0] += 1
+        e[1] += h
+        e[2] += miss.get(d, 0.0)
+    rows = []
+    for k, (n, h, m) in per.items():
+        rows.append((k, n, h / n, m / n, h / (h + m) if h + m > 0 else 0.0))
+    rows.sort(key=lambda r: -(r[2] + r[3]) * r[1])
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("trace")
     t.add_argument("stats_csv")
+    l2 = sub.add_parser("l2")
+    l2.add_argument("counter_csv")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_csv")
     c.add_argument("write_csv")
@@ -169,7 +189,11 @@ def main(argv=None):
     c.add_argument("--workload", default="c1")
     c.add_argument("--command", default="")
     a = ap.parse_args(argv)
-    if a.cmd == "trace":
+    if a.cmd == "l2":
+        print(f"{'kernel':44s} {'calls':>6s} {'hits/disp':>12s} {'misses/disp':>12s} {'hit rate':>9s}")
+        for k, n, h, m, r in l2_table(a.counter_csv):
+            print(f"{k:44s} {n:6d} {h:12.0f} {m:12.0f} {r:9.3f}")
+    elif a.cmd == "trace":
         rows = read_trace(a.stats_csv)
         print(f"{'kernel':44s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}")
         for r in rows:

@@ -1,0 +1,95 @@
+// Host check of the compact XCD-sliced format (slice_format, count_compact)
+// and of the combine kernel's partial-sum indexing, on random segmented
+// matrices with empty, short and very long segments:
+//   * the compact segment count equals count_compact;
+//   * every compact segment is covered by exactly one tile (or one first
+//     piece of a split), tiles stay inside their slice's compact range and
+//     their nonzero range matches the pointers;
+//   * every sliced nonzero lies in its slice's index range and src points
+//     back to the same index in the unsliced format;
+//   * the combine's position rule (cbase of the 256-segment block plus the
+//     count of earlier segments of the block with that slice bit) stays in
+//     range and adds up to the unsliced segment sum.
+// Built with g++ (AddressSanitizer, UBSan) by tests/test_host_cpu.py.
+#include "dpdlp_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <random>
+
+using namespace dpdlp;
+
+int main()
+{
+    std::mt19937_64 rng(1);
+    int bad = 0;
+    for (int trial = 0; trial < 60; ++trial) {
+        const int nseg = 1 + (int)(rng() % 3000), nidx = 1 + (int)(rng() % 5000);
+        const int S = 8 * (1 + (int)(rng() % 3));
+        hvec<int32_t> ptr((size_t)nseg + 1), idx;
+        ptr[0] = 0;
+        for (int g = 0; g < nseg; ++g) {
+            int len = (rng() % 10 == 0) ? (int)(rng() % 5000) : (int)(rng() % 12);
+            if (rng() % 7 == 0) len = 0;
+            std::vector<int> cols;
+            for (int q = 0; q < len; ++q) cols.push_back((int)(rng() % nidx));
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            for (int c : cols) idx.push_back(c);
+            ptr[(size_t)g + 1] = (int32_t)idx.size();
+        }
+        std::vector<double> val(idx.size()), v((size_t)nidx);
+        for (auto &a : val) a = (double)(rng() % 1000) / 7.0;
+        for (auto &a : v) a = (double)(rng() % 1000) / 3.0;
+        SlicedHost sh;
+        const int tile = 64 << (rng() % 6);
+        slice_format(ptr, idx, nseg, nidx, S, tile, sh);
+        if (sh.G != count_compact(ptr, idx, nseg, nidx, S)) { std::printf("G mismatch\n"); ++bad; }
+        std::vector<int> cover((size_t)sh.G, 0);
+        for (const Tile &t : sh.tiles) {
+            if (t.seg_begin < sh.seg_base[(size_t)t.slice] || t.seg_end > sh.seg_base[(size_t)t.slice + 1]) {
+                std::printf("tile outside its slice\n");
+                ++bad;
+                continue;
+            }
+            for (int g = t.seg_begin; g < t.seg_end; ++g) cover[(size_t)g] += t.npieces ? (t.piece == 0) : 1;
+            if (t.nnz_begin < sh.ptr[(size_t)t.seg_begin] || t.nnz_end > sh.ptr[(size_t)t.seg_end]) {
+                std::printf("tile nonzero range\n");
+                ++bad;
+            }
+        }
+        for (int64_t g = 0; g < sh.G; ++g)
+            if (cover[(size_t)g] != 1) { std::printf("cover %ld: %d\n", (long)g, cover[(size_t)g]); ++bad; break; }
+        std::vector<double> part((size_t)sh.G, 0.0);
+        for (int s = 0; s < S; ++s)
+            for (int64_t g = sh.seg_base[(size_t)s]; g < sh.seg_base[(size_t)s + 1]; ++g)
+                for (int p = sh.ptr[(size_t)g]; p < sh.ptr[(size_t)g + 1]; ++p) {
+                    if (sh.idx[(size_t)p] / sh.size != s) { std::printf("index outside slice\n"); ++bad; }
+                    if (idx[(size_t)sh.src[(size_t)p]] != sh.idx[(size_t)p]) { std::printf("src\n"); ++bad; }
+                    part[(size_t)g] += val[(size_t)sh.src[(size_t)p]] * v[(size_t)sh.idx[(size_t)p]];
+                }
+        const int nblk = (nseg + 255) / 256;
+        for (int b = 0; b < nblk; ++b)
+            for (int t = 0; t < 256; ++t) {
+                const int j = b * 256 + t;
+                if (j >= nseg) break;
+                double r = 0.0, ref = 0.0;
+                for (int s = 0; s < S; ++s) {
+                    const int pl = s / 8, bit = s % 8;
+                    if (!((sh.mask[(size_t)pl * nseg + j] >> bit) & 1)) continue;
+                    int off = sh.cbase[(size_t)b * S + s];
+                    for (int u = b * 256; u < j; ++u) off += (sh.mask[(size_t)pl * nseg + u] >> bit) & 1;
+                    if (off < 0 || off >= sh.G) { std::printf("partial index out of range\n"); ++bad; continue; }
+                    r += part[(size_t)off];
+                }
+                for (int p = ptr[(size_t)j]; p < ptr[(size_t)j + 1]; ++p) ref += val[(size_t)p] * v[(size_t)idx[(size_t)p]];
+                if (std::fabs(r - ref) > 1e-9 * (1 + std::fabs(ref))) {
+                    if (bad < 5) std::printf("segment %d: %g vs %g\n", j, r, ref);
+                    ++bad;
+                }
+            }
+    }
+    std::printf(bad ? "FAILED %d\n" : "ok\n", bad);
+    return bad != 0;
+}

@@ -145,3 +145,26 @@ def test_create_without_gpu_fails_loudly(D):
         pytest.skip("a GPU is present")
     with pytest.raises(D.DpdlpError):
         D.Problem(lpgen.config0())
+
+
+@pytest.mark.parametrize("prog", ["slice_format_check", "bidiag_check"])
+def test_host_cpp_checks(tmp_path, prog):
+    """Host-side C++ checks built with g++ and the sanitizers (no GPU code):
+    the compact sliced format with the combine's indexing, and the Lanczos
+    bidiagonal helpers (see the sources under tests/host_cpp/)."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, "paper_2601_07628_amd", "csrc")
+    exe = str(tmp_path / prog)
+    cmd = [gxx, "-O1", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I", os.path.join(root, "include"), "-I", csrc,
+           os.path.join(root, "tests", "host_cpp", prog + ".cpp"),
+           os.path.join(csrc, "dpdlp_host.cpp"), "-o", exe, "-lpthread"]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=300)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout[-2000:] + out.stderr[-2000:]
+    assert out.stdout.strip().endswith("ok")
