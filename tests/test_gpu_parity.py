@@ -249,34 +249,41 @@ def test_split_segments_long_row_and_column(D, O):
     fixed_run(D, O, lp, 300, gpu_kw=dict(tile_nnz=512, gather_slices=8))
 
 
-def test_edge_cases_empty_rows_cols_free_rows(D, O):
+@pytest.mark.parametrize("slices", [-1, 8, 16])
+def test_edge_cases_empty_rows_cols_free_rows(D, O, slices):
+    """Empty rows and columns, free rows; sliced: most slices hold no
+    nonzero at all (5 columns, 4 rows over 8 or 16 slices)."""
     A = np.array([[1.0, 0, 1, 0, 0], [0, 0, 0, 0, 0], [1, 0, -1, 0, 2], [0, 0, 0, 0, 0]])
     lp = lpgen.from_dense(A, [1.0, 2.0, -1.0, -3.0, 0.5], [1.0, -np.inf, -1.0, -np.inf],
                           [1.0, np.inf, np.inf, np.inf], [0] * 5, [5] * 5)
-    fixed_run(D, O, lp, 200)
-    G = D.Problem(lp, gpu_params(D, eps=1e-10))
+    fixed_run(D, O, lp, 200, gpu_kw=dict(gather_slices=slices))
+    G = D.Problem(lp, gpu_params(D, eps=1e-10, gather_slices=slices))
     r = G.solve()
     o = O.Problem(lp, oracle_params(O, eps=1e-10)).solve()
     assert r["status"] == 1 and o["status"] == 1
     assert abs(r["obj_primal"] - o["obj_p"]) < 1e-8
 
 
-def test_single_row_and_single_column(D, O):
+@pytest.mark.parametrize("slices", [-1, 8])
+def test_single_row_and_single_column(D, O, slices):
+    """One row of 5000 nonzeros and one column of 4000 (split over tiles;
+    sliced: split within a slice, and 1-wide index ranges)."""
     rng = np.random.default_rng(11)
     n = 5000                                   # one row of 5000 nonzeros (split)
     w = rng.uniform(1, 10, n)
     lp = lpgen.from_dense(w[None, :], -rng.uniform(1, 10, n), [-np.inf], [0.4 * w.sum()],
                           np.zeros(n), np.ones(n))
-    fixed_run(D, O, lp, 300)
+    fixed_run(D, O, lp, 300, gpu_kw=dict(gather_slices=slices))
     m = 4000                                   # one column of 4000 nonzeros (split)
     a = rng.standard_normal(m)
     lp = lpgen.from_dense(a[:, None], [1.0], a * 0.5 - 1, a * 0.5 + 1, [-2.0], [2.0])
-    fixed_run(D, O, lp, 300)
+    fixed_run(D, O, lp, 300, gpu_kw=dict(gather_slices=slices))
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_tiny_lps(D, O, seed):
-    fixed_run(D, O, lpgen.tiny_lp(seed), 500)
+@pytest.mark.parametrize("slices", [-1, 8])
+def test_tiny_lps(D, O, seed, slices):
+    fixed_run(D, O, lpgen.tiny_lp(seed), 500, gpu_kw=dict(gather_slices=slices))
 
 
 # ---- solves ----------------------------------------------------------------------
