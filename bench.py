@@ -331,6 +331,27 @@ def main():
         extra["time_to_1e-4_c1"] = out
         log(f"c1 time to 1e-4 (45 s cap): {out}")
 
+    def c2_rate():
+        # the transportation LP (9M columns, rows of 3000 nonzeros): its
+        # gathers are cheap (y is 48 KB; x is read in long contiguous runs),
+        # so its fused steps show what the tile kernels reach on HBM bytes
+        lp2 = lpgen.config2()
+        G2 = D.Problem(lp2, gpu_params(D, eps=1e-8, max_iters=10**9), stream=stream)
+        G2.init()
+        G2.iterate(ips)
+        G2.profile_enable(True)
+        n2 = max(5, args.steps // 2)
+        el2 = timed_steps(G2, n2, ips, torch)
+        p2 = G2.profile()
+        k2 = {k: dict(avg_ms=round(v["total_ms"] / v["launches"], 5),
+                      alg_GBps=round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"]) / 1e6, 1))
+              for k, v in p2.items() if v["launches"] and v["bytes_per_launch"]}
+        extra["c2_fp64"] = {"iters_per_s": round(n2 * ips / el2, 1), "kernels": k2,
+                            "primal_roofline_frac": round(k2["primal"]["alg_GBps"] / HBM_PEAK_GBS, 4),
+                            "dual_roofline_frac": round(k2["dual"]["alg_GBps"] / HBM_PEAK_GBS, 4)}
+        log(f"c2 FP64: {extra['c2_fp64']}")
+        G2.close()
+
     def ws():
         full = args.ws_train >= 384
         extra["warm_start_c4"] = warmstart_eval(
@@ -341,6 +362,7 @@ def main():
         for S in (0, 8):
             guarded(f"fp64_gather_slices_{S}", lambda S=S: sliced(S))
         guarded("fp32_mixed_c1", fp32)
+        guarded("c2_fp64", c2_rate)
         for name, mk in (("c0", lpgen.config0), ("c4", lpgen.config4)):
             guarded(f"time_to_tol_{name}", lambda name=name, mk=mk: ttt(name, mk))
         if not args.no_c1_ttt:
