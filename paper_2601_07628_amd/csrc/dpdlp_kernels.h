@@ -144,13 +144,17 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op0, const Tile *__restrict_
     const int nseg = d.seg_end - d.seg_begin;
     const bool whole = d.npieces == 0;
 
+    // Every load of phase 1 is unconditional, from an index clamped into the
+    // tile (lanes past its end repeat its last element and store nothing),
+    // so that each group of loads issues back to back and is waited for
+    // once; per-element branches would put a wait after every load.
     // 1a. issue the tile's matrix stream (coalesced, non-temporal)
     int jj[kPer];
     MT aa[kPer];
+    if (cnt > 0) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int e = threadIdx.x + q * kBlock;
-        if (e < cnt) {
+        for (int q = 0; q < kPer; ++q) {
+            const int e = min((int)threadIdx.x + q * kBlock, cnt - 1);
             jj[q] = nt_load(idx + nnz0 + e);
             aa[q] = nt_load(val + nnz0 + e);
         }
@@ -158,22 +162,32 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op0, const Tile *__restrict_
     // 1b. segment pointers to LDS and the epilogue's vector loads
     typename Op::Pre pre[kPre];
     if (whole) {
-        for (int s = threadIdx.x; s <= nseg; s += kBlock) s_ptr[s] = seg_ptr[d.seg_begin + s] - nnz0;
+        constexpr int kPtrIt = (kMaxSegs + kBlock) / kBlock;   // covers nseg + 1 <= kMaxSegs + 1
+        int sp[kPtrIt];
 #pragma unroll
-        for (int q = 0; q < kPre; ++q) {
-            const int s = threadIdx.x + q * kBlock;
-            if (s < nseg) op.prefetch(d.seg_begin + s, pre[q]);
+        for (int i = 0; i < kPtrIt; ++i)
+            sp[i] = seg_ptr[d.seg_begin + min((int)threadIdx.x + i * kBlock, nseg)];
+#pragma unroll
+        for (int q = 0; q < kPre; ++q)
+            op.prefetch(d.seg_begin + min((int)threadIdx.x + q * kBlock, nseg - 1), pre[q]);
+#pragma unroll
+        for (int i = 0; i < kPtrIt; ++i) {
+            const int s = threadIdx.x + i * kBlock;
+            if (s <= nseg) s_ptr[s] = sp[i] - nnz0;
         }
     }
-    // 1c. gathers, products to LDS
+    // 1c. gathers (all issued before the first product is stored), products to LDS
+    if (cnt > 0) {
+        AT pv[kPer][NR];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int e = threadIdx.x + q * kBlock;
-        if (e < cnt) {
-            AT v[NR];
-            op.value(aa[q], jj[q], v);
+        for (int q = 0; q < kPer; ++q) op.value(aa[q], jj[q], pv[q]);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) s_prod[r][e] = v[r];
+        for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < cnt) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) s_prod[r][e] = pv[q][r];
+            }
         }
     }
     __syncthreads();
@@ -457,14 +471,22 @@ __global__ __launch_bounds__(kBlock) void k_combine(Op op0, int nseg, int S,
             if (lane == 0) s_cnt[b][wave] = __popcll(bal[b]);
         }
         __syncthreads();
+        // positions of all 8 slices first, then all loads (absent slices
+        // load partial[0], always allocated, and add nothing), then the sums
+        // in slice order
+        int off[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            if ((mb >> b) & 1u) {
-                int off = cb[pl * 8 + b] + __popcll(bal[b] & below);
-                for (int w = 0; w < wave; ++w) off += s_cnt[b][w];
-                r[0] += partial[off];
-            }
+            int o = cb[pl * 8 + b] + __popcll(bal[b] & below);
+            for (int w = 0; w < wave; ++w) o += s_cnt[b][w];
+            off[b] = ((mb >> b) & 1u) ? o : 0;
         }
+        AT pv[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) pv[b] = partial[off[b]];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            if ((mb >> b) & 1u) r[0] += pv[b];
         __syncthreads();
     }
     double acc[1];
