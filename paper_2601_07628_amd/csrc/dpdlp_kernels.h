@@ -437,20 +437,52 @@ struct PartialOp {
     }
 };
 
+// Per-slice segment sums of two right-hand sides (the sliced CSR check
+// pass: A~ xh and A~ dx); the second one is stored G entries after the first.
+struct PartialOp2 {
+    using MT = double; using AT = double; using R = SumOp;
+    static constexpr int NR = 2, NQ = 0;
+    int slice = 0;
+    __device__ void resolve() {}
+    const double *__restrict__ v;
+    const double *__restrict__ v2;
+    double *__restrict__ partial;
+    int64_t G;
+    double *partials;
+    using Pre = NoPre;
+    __device__ void value(MT a, int j, AT *o) const
+    {
+        o[0] = a * v[j];
+        o[1] = a * v2[j];
+    }
+    __device__ void prefetch(int, Pre &) const {}
+    __device__ void epilogue(int g, const AT *r, const Pre &, double *) const
+    {
+        partial[g] = r[0];
+        partial[G + g] = r[1];
+    }
+};
+
 // Adds the slice partials of each segment in slice order and runs a fused
-// epilogue (PrimalOp / DualOp) on the sum; one thread per segment.  The
-// partials are compact (only the slices where the segment has nonzeros):
-// the position of segment j's partial in slice s is cbase[block * S + s]
-// plus the number of segments of this block before j that have slice s,
-// counted with wave ballots over the mask bits.
+// epilogue (PrimalOp / DualOp, or a check pass) on the sums; one thread per
+// segment.  The partials are compact (only the slices where the segment has
+// nonzeros): the position of segment j's partial in slice s is
+// cbase[block * S + s] plus the number of segments of this block before j
+// that have slice s, counted with wave ballots over the mask bits.  With
+// Op::NR = 2 the second right-hand side's partials start G entries later.
+// Ops with NQ > 0 (check passes) leave per-block partial sums in
+// op.partials[q * gridDim.x + block].
 template <class Op>
 __global__ __launch_bounds__(kBlock) void k_combine(Op op0, int nseg, int S,
                                                     const typename Op::AT *__restrict__ partial,
                                                     const uint8_t *__restrict__ mask,
-                                                    const int *__restrict__ cbase)
+                                                    const int *__restrict__ cbase, int64_t G)
 {
     using AT = typename Op::AT;
+    constexpr int NR = Op::NR;
+    constexpr int NQ = Op::NQ > 0 ? Op::NQ : 1;
     __shared__ int s_cnt[8][kBlock / 64];
+    __shared__ double s_red[NQ][kBlock / 64];
     const int j = blockIdx.x * kBlock + threadIdx.x;
     const bool in = j < nseg;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -459,8 +491,9 @@ __global__ __launch_bounds__(kBlock) void k_combine(Op op0, int nseg, int S,
     op.resolve();
     typename Op::Pre p;
     if (in) op.prefetch(j, p);
-    AT r[1];
-    r[0] = SumOp::template id<AT>();
+    AT r[NR];
+#pragma unroll
+    for (int z = 0; z < NR; ++z) r[z] = SumOp::template id<AT>();
     const int *cb = cbase + (size_t)blockIdx.x * S;
     for (int pl = 0; pl < S / 8; ++pl) {
         const unsigned mb = in ? (unsigned)mask[(size_t)pl * nseg + j] : 0u;
@@ -481,16 +514,27 @@ __global__ __launch_bounds__(kBlock) void k_combine(Op op0, int nseg, int S,
             for (int w = 0; w < wave; ++w) o += s_cnt[b][w];
             off[b] = ((mb >> b) & 1u) ? o : 0;
         }
-        AT pv[8];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) pv[b] = partial[off[b]];
+        AT pv[8][NR];
 #pragma unroll
         for (int b = 0; b < 8; ++b)
-            if ((mb >> b) & 1u) r[0] += pv[b];
+#pragma unroll
+            for (int z = 0; z < NR; ++z) pv[b][z] = partial[(size_t)z * G + off[b]];
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            if ((mb >> b) & 1u)
+#pragma unroll
+                for (int z = 0; z < NR; ++z) r[z] += pv[b][z];
         __syncthreads();
     }
-    double acc[1];
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     if (in) op.epilogue(j, r, p, acc);
+    if (Op::NQ > 0) {
+        block_reduce<SumOp, NQ>(acc, s_red);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < Op::NQ; ++q) op.partials[(size_t)q * gridDim.x + blockIdx.x] = acc[q];
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -372,6 +372,7 @@ struct dpdlp_problem {
     TileSet tr, tc;
     SlicedSet sr, sc;               // XCD-sliced CSR (dual) and CSC (primal)
     void *part_slices = nullptr;    // compact per-slice segment sums
+    int chk_nr = 0, chk_nc = 0;     // partial-sum entries of the last check passes
     void *carries = nullptr;
     double *part_r = nullptr, *part_c = nullptr;
     int *perm_row = nullptr, *perm_col = nullptr;
@@ -535,7 +536,7 @@ static void launch_primal(dpdlp_problem *P, const T *y, const T *c, const T *lo,
         launch_tiles(P, po, P->sc.ts, P->sc.ptr, P->sc.idx,
                      (const T *)(sizeof(T) == 8 ? (const void *)P->sc.val : (const void *)P->sc.val32));
         hipLaunchKernelGGL(k_combine<PrimalOp<T>>, dim3(nblk(P->n)), dim3(kBlock), 0, P->s, op, P->n,
-                           P->sc.S, (const T *)P->part_slices, P->sc.mask, P->sc.cbase);
+                           P->sc.S, (const T *)P->part_slices, P->sc.mask, P->sc.cbase, P->sc.G);
         return;
     }
     launch_tiles(P, op, P->tc, P->cp, P->ri, vt);
@@ -562,7 +563,7 @@ static void launch_dual(dpdlp_problem *P, const T *xbar, const T *lo, const T *h
         launch_tiles(P, po, P->sr.ts, P->sr.ptr, P->sr.idx,
                      (const T *)(sizeof(T) == 8 ? (const void *)P->sr.val : (const void *)P->sr.val32));
         hipLaunchKernelGGL(k_combine<DualOp<T>>, dim3(nblk(P->m)), dim3(kBlock), 0, P->s, op, P->m,
-                           P->sr.S, (const T *)P->part_slices, P->sr.mask, P->sr.cbase);
+                           P->sr.S, (const T *)P->part_slices, P->sr.mask, P->sr.cbase, P->sr.G);
         return;
     }
     launch_tiles(P, op, P->tr, P->rp, P->ci, v);
@@ -631,6 +632,10 @@ static void drop_graphs(dpdlp_problem *P)
 
 // Check passes at (xh, yh, dx, dy) against the anchor (xa_any, ya_any).
 template <typename TA>
+// The check passes, on the XCD-sliced formats where the fused steps use
+// them (partial sums per slice, then a combine that runs the check's
+// epilogue).  Sets chk_nr / chk_nc, the number of partial-sum entries per
+// quantity that k_control adds.
 static void launch_checks(dpdlp_problem *P, const double *xh, const double *dx, const double *yh,
                           const double *dy, const TA *xa, const TA *ya, double tau)
 {
@@ -639,14 +644,37 @@ static void launch_checks(dpdlp_problem *P, const double *xh, const double *dx, 
         CheckRowOp<TA> op;
         op.xh = xh; op.dx = dx; op.yh = yh; op.dy = dy; op.ya = ya;
         op.dr = P->dr; op.lo0 = P->clo0; op.hi0 = P->chi0; op.partials = P->part_r;
-        launch_tiles(P, op, P->tr, P->rp, P->ci, P->v);
+        if (P->sr.S > 0) {
+            PartialOp2 po;
+            po.v = xh; po.v2 = dx; po.partial = (double *)P->part_slices; po.G = P->sr.G;
+            po.partials = nullptr;
+            launch_tiles(P, po, P->sr.ts, P->sr.ptr, P->sr.idx, P->sr.val);
+            hipLaunchKernelGGL(k_combine<CheckRowOp<TA>>, dim3(nblk(P->m)), dim3(kBlock), 0, P->s, op,
+                               P->m, P->sr.S, (const double *)P->part_slices, P->sr.mask,
+                               P->sr.cbase, P->sr.G);
+            P->chk_nr = nblk(P->m);
+        } else {
+            launch_tiles(P, op, P->tr, P->rp, P->ci, P->v);
+            P->chk_nr = P->tr.n;
+        }
     }
     {
         ProfScope ps(P, 3);
         CheckColOp<TA> op;
         op.yh = yh; op.xh = xh; op.dx = dx; op.xa = xa; op.c = P->c; op.c0 = P->c0;
         op.lo = P->vlo; op.hi = P->vhi; op.dc = P->dc; op.partials = P->part_c; op.tau = tau;
-        launch_tiles(P, op, P->tc, P->cp, P->ri, P->vt);
+        if (P->sc.S > 0) {
+            PartialOp<double> po;
+            po.v = yh; po.partial = (double *)P->part_slices; po.partials = nullptr;
+            launch_tiles(P, po, P->sc.ts, P->sc.ptr, P->sc.idx, P->sc.val);
+            hipLaunchKernelGGL(k_combine<CheckColOp<TA>>, dim3(nblk(P->n)), dim3(kBlock), 0, P->s, op,
+                               P->n, P->sc.S, (const double *)P->part_slices, P->sc.mask,
+                               P->sc.cbase, P->sc.G);
+            P->chk_nc = nblk(P->n);
+        } else {
+            launch_tiles(P, op, P->tc, P->cp, P->ri, P->vt);
+            P->chk_nc = P->tc.n;
+        }
     }
 }
 
@@ -1000,13 +1028,15 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     if (Sp) CHK(build_sliced(P, H.cp, H.ri, n, m, Sp, P->sc));     // primal: gathers y
     if (Sd || Sp) {
         ntmax = std::max(ntmax, std::max(P->sr.ts.n, P->sc.ts.n));
-        const size_t ps = (size_t)std::max<int64_t>(1, std::max(P->sr.G, P->sc.G));
+        // the sliced CSR check pass keeps two right-hand sides (2 G doubles)
+        const size_t ps = (size_t)std::max<int64_t>(1, std::max(2 * P->sr.G, P->sc.G));
         CHK(dalloc(P, (double **)&P->part_slices, ps));
     }
     // split-piece carries (2 right-hand sides) and per-tile partial sums
     CHK(dalloc(P, (double **)&P->carries, (size_t)2 * std::max(ntmax, 1)));
-    CHK(dalloc(P, &P->part_r, (size_t)kNQ * std::max(P->tr.n, 1)));
-    CHK(dalloc(P, &P->part_c, (size_t)kNQ * std::max(P->tc.n, 1)));
+    // per-tile (or, sliced, per-combine-block) partial sums of the checks
+    CHK(dalloc(P, &P->part_r, (size_t)kNQ * std::max(std::max(P->tr.n, (int)nblk(m)), 1)));
+    CHK(dalloc(P, &P->part_c, (size_t)kNQ * std::max(std::max(P->tc.n, (int)nblk(n)), 1)));
     CHK(dalloc(P, &P->perm_row, (size_t)m)); CHK(dalloc(P, &P->perm_col, (size_t)n));
     CHK(upload(P, P->perm_row, H.perm_row.data(), sizeof(int32_t) * (size_t)m));
     CHK(upload(P, P->perm_col, H.perm_col.data(), sizeof(int32_t) * (size_t)n));
@@ -1213,8 +1243,8 @@ static int iterate_impl(dpdlp_problem *P, int64_t n_iters)
         else launch_checks<double>(P, P->xh, P->dx, P->yh, P->dy, P->xa, P->ya, tau);
         {
             ProfScope ps(P, 4);
-            hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, P->s, P->part_r, P->tr.n,
-                               P->part_c, P->tc.n, P->ctl, ctl_args(P, 0));
+            hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, P->s, P->part_r, P->chk_nr,
+                               P->part_c, P->chk_nc, P->ctl, ctl_args(P, 0));
         }
         hipError_t le = hipGetLastError();
         if (le != hipSuccess) return hip_fail(le, "kernel launch");
@@ -1603,8 +1633,8 @@ int dpdlp_kkt(dpdlp_problem *P, const double *x, const double *y, double tau, in
     // evaluate into a scratch control block so the solver state is untouched
     HIPCHK(hipMemsetAsync(P->ctl_eval, 0, sizeof(Control), P->s));
     CtlArgs a = ctl_args(P, 1);
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, P->s, P->part_r, P->tr.n, P->part_c,
-                       P->tc.n, P->ctl_eval, a);
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, P->s, P->part_r, P->chk_nr, P->part_c,
+                       P->chk_nc, P->ctl_eval, a);
     Control h;
     HIPCHK(hipMemcpyAsync(&h, P->ctl_eval, sizeof(Control), hipMemcpyDeviceToHost, P->s));
     HIPCHK(hipStreamSynchronize(P->s));
