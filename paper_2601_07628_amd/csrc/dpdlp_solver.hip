@@ -630,12 +630,34 @@ static void drop_graphs(dpdlp_problem *P)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
-// Check passes at (xh, yh, dx, dy) against the anchor (xa_any, ya_any).
-template <typename TA>
-// The check passes, on the XCD-sliced formats where the fused steps use
+// A single-right-hand-side product pass with a per-segment epilogue (SpmvOp,
+// LanczosOp: out = f(A~ in) and per-block sums of out^2), on the XCD-sliced
+// format when that product has one.  transpose: A~^T (CSC, segments are
+// columns).  Returns the number of partial-sum entries left in op.partials.
+template <class Op>
+static int launch_product(dpdlp_problem *P, bool transpose, const Op &op, const double *in)
+{
+    const SlicedSet &ss = transpose ? P->sc : P->sr;
+    const int nseg = transpose ? P->n : P->m;
+    if (ss.S > 0) {
+        PartialOp<double> po;
+        po.v = in; po.partial = (double *)P->part_slices; po.partials = nullptr;
+        launch_tiles(P, po, ss.ts, ss.ptr, ss.idx, ss.val);
+        hipLaunchKernelGGL(k_combine<Op>, dim3(nblk(nseg)), dim3(kBlock), 0, P->s, op, nseg, ss.S,
+                           (const double *)P->part_slices, ss.mask, ss.cbase, ss.G);
+        return (int)nblk(nseg);
+    }
+    if (transpose) launch_tiles(P, op, P->tc, P->cp, P->ri, P->vt);
+    else launch_tiles(P, op, P->tr, P->rp, P->ci, P->v);
+    return transpose ? P->tc.n : P->tr.n;
+}
+
+// Check passes at (xh, yh, dx, dy) against the anchor (xa_any, ya_any),
+// on the XCD-sliced formats where the fused steps use
 // them (partial sums per slice, then a combine that runs the check's
 // epilogue).  Sets chk_nr / chk_nc, the number of partial-sum entries per
 // quantity that k_control adds.
+template <typename TA>
 static void launch_checks(dpdlp_problem *P, const double *xh, const double *dx, const double *yh,
                           const double *dy, const TA *xa, const TA *ya, double tau)
 {
@@ -808,14 +830,14 @@ static int lanczos_sigma(dpdlp_problem *P, uint64_t seed, int max_steps, double 
             LanczosOp a;
             a.in = w; a.out = z; a.nin = beta; a.nprev = alpha; a.first = k == 1;
             a.partials = P->part_r;
-            launch_tiles(P, a, P->tr, P->rp, P->ci, P->v);
-            hipLaunchKernelGGL(k_lanczos_norm, dim3(1), dim3(kBlock), 0, P->s, P->part_r, P->tr.n,
+            const int na = launch_product(P, false, a, w);
+            hipLaunchKernelGGL(k_lanczos_norm, dim3(1), dim3(kBlock), 0, P->s, P->part_r, na,
                                alpha, ha, k);
             LanczosOp b;
             b.in = z; b.out = w; b.nin = alpha; b.nprev = beta; b.first = 0;
             b.partials = P->part_c;
-            launch_tiles(P, b, P->tc, P->cp, P->ri, P->vt);
-            hipLaunchKernelGGL(k_lanczos_norm, dim3(1), dim3(kBlock), 0, P->s, P->part_c, P->tc.n,
+            const int nb = launch_product(P, true, b, z);
+            hipLaunchKernelGGL(k_lanczos_norm, dim3(1), dim3(kBlock), 0, P->s, P->part_c, nb,
                                beta, hb, k + 1);
         }
         HIPCHK(hipGetLastError());
@@ -1589,8 +1611,7 @@ int dpdlp_spmv(dpdlp_problem *P, int32_t transpose, const double *in, double *ou
                        transpose ? P->perm_row : P->perm_col, (const double *)nullptr, pin);
     SpmvOp op; op.in = pin; op.div = nullptr; op.out = pout;
     op.partials = transpose ? P->part_c : P->part_r;
-    if (transpose) launch_tiles(P, op, P->tc, P->cp, P->ri, P->vt);
-    else launch_tiles(P, op, P->tr, P->rp, P->ci, P->v);
+    launch_product(P, transpose != 0, op, pin);
     hipLaunchKernelGGL(k_unpermute<double>, dim3(nblk(kout)), dim3(kBlock), 0, P->s, kout, pout,
                        transpose ? P->perm_col : P->perm_row, (const double *)nullptr, out);
     HIPCHK(hipGetLastError());
@@ -1688,10 +1709,10 @@ int dpdlp_time_kernel(dpdlp_problem *P, int32_t which, int32_t reps, void *strea
             else launch_dual<double>(P, P->xbar, P->clo, P->chi, P->ya, P->tmp_m, P->v, sigma, 5, 0);
         } else if (which == 2) {
             SpmvOp op; op.in = P->x; op.div = nullptr; op.out = P->tmp_m; op.partials = P->part_r;
-            launch_tiles(P, op, P->tr, P->rp, P->ci, P->v);
+            launch_product(P, false, op, P->x);
         } else {
             SpmvOp op; op.in = P->y; op.div = nullptr; op.out = P->tmp_n; op.partials = P->part_c;
-            launch_tiles(P, op, P->tc, P->cp, P->ri, P->vt);
+            launch_product(P, true, op, P->y);
         }
     };
     // the in-place update on scratch copies needs valid data in them
