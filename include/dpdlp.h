@@ -112,10 +112,13 @@ typedef struct dpdlp_params {
                               /* XCD s % 8, partial sums added per segment in */
                               /* slice order (the 2-D partition of Sec. 3.1  */
                               /* across the 8 XCDs).  Automatic slices a step */
-                              /* (S = 8) when its gathered vector exceeds 4 MB */
-                              /* and its partial sums, one per (segment,      */
-                              /* slice) with nonzeros at 20 bytes each, cost  */
-                              /* less than its 12 bytes per nonzero.          */
+                              /* when its gathered vector exceeds 4 MB and   */
+                              /* its partial sums, one per (segment, slice)  */
+                              /* with nonzeros at 20 bytes each, cost less   */
+                              /* than its 12 bytes per nonzero: S = 16 when  */
+                              /* 8 slices would exceed 2 MB each (in the     */
+                              /* iterate's precision) and each gathered      */
+                              /* element is read >= 4 times per pass, else 8 */
     int32_t use_graphs;       /* 1: replay the check_period - 1 iterations    */
                               /* between two checks as one HIP graph (off    */
                               /* while dpdlp_profile_enable is on)           */

@@ -1027,10 +1027,12 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     CHK(build_tileset(P, H.cp, n, P->tc, ht));
     int ntmax = std::max(P->tr.n, P->tc.n);
     // XCD-sliced fused steps: S > 0 slices both steps; S < 0 (automatic)
-    // slices a step with S = 8 when its gathered vector exceeds one XCD's L2
-    // (4 MB) and its compact partial sums (written and read, 8 + 8 bytes, plus
-    // a 4-byte pointer per compact segment) cost less than its matrix stream
-    // (12 bytes per nonzero); never when the gathered dimension
+    // slices a step when its gathered vector exceeds one XCD's L2 (4 MB) and
+    // its compact partial sums (written and read, 8 + 8 bytes, plus a 4-byte
+    // pointer per compact segment) cost less than its matrix stream (12
+    // bytes per nonzero), with S = 16 where 8 slices would still leave more
+    // than 2 MB per slice (in the iterate's precision) of a vector that is
+    // gathered at least 4 times per pass, else S = 8; never when the gathered dimension
     // is in hot-first order (equal index ranges would put most nonzeros in
     // one slice, and the order itself gives the cache locality).
     int Sd = 0, Sp = 0;                 // dual (CSR, gathers x), primal (CSC, gathers y)
@@ -1042,9 +1044,20 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         Sd = Sp = P->prm.gather_slices;
     } else if (P->prm.gather_slices < 0) {
         const double mat = 12.0 * (double)nnz, l2 = 4.0 * (1 << 20);
+        const double eb = P->prm.precision == DPDLP_FP32_MIXED ? 4.0 : 8.0;   // gathered element
         const bool hot_rows = P->prm.perm_order & 1, hot_cols = P->prm.perm_order & 2;
-        if (!hot_cols && 8.0 * n > l2 && 20.0 * (double)count_compact(H.rp, H.ci, m, n, 8) < mat) Sd = 8;
-        if (!hot_rows && 8.0 * m > l2 && 20.0 * (double)count_compact(H.cp, H.ri, n, m, 8) < mat) Sp = 8;
+        auto pick = [&](const hvec<int32_t> &ptr, const hvec<int32_t> &idx, int32_t nseg,
+                        int32_t nidx) -> int {
+            if (8.0 * nidx <= l2) return 0;
+            // 16 slices when 8 would leave more than half an L2 per slice and
+            // each gathered element is read at least 4 times per pass
+            int S = (eb * nidx / 8.0 > l2 / 2 && (double)nnz >= 4.0 * nidx) ? 16 : 8;
+            for (; S >= 8; S /= 2)
+                if (20.0 * (double)count_compact(ptr, idx, nseg, nidx, S) < mat) return S;
+            return 0;
+        };
+        if (!hot_cols) Sd = pick(H.rp, H.ci, m, n);
+        if (!hot_rows) Sp = pick(H.cp, H.ri, n, m);
     }
     if (Sd) CHK(build_sliced(P, H.rp, H.ci, m, n, Sd, P->sr));     // dual: gathers xbar
     if (Sp) CHK(build_sliced(P, H.cp, H.ri, n, m, Sp, P->sc));     // primal: gathers y

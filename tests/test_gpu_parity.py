@@ -112,10 +112,13 @@ def test_scaling_matches_oracle(D, O):
 
 
 @pytest.mark.parametrize("transpose", [False, True])
-def test_spmv_matches_oracle(D, O, transpose):
+@pytest.mark.parametrize("slices", [-1, 8, 16])
+def test_spmv_matches_oracle(D, O, transpose, slices):
+    """A~ v and A~^T v against the oracle, unsliced (the automatic rule does
+    not slice this size) and through the sliced partial + combine kernels."""
     import torch
     lp = lpgen.huge_share_lp(m=30000, n=60000, seed=8)
-    G = D.Problem(lp, gpu_params(D, eta=1.0, omega0=1.0))
+    G = D.Problem(lp, gpu_params(D, eta=1.0, omega0=1.0, gather_slices=slices))
     P = O.Problem(lp, oracle_params(O, eta=1.0, omega0=1.0))
     rng = np.random.default_rng(0)
     v = rng.standard_normal(lp.m if transpose else lp.n)
@@ -128,7 +131,8 @@ def test_spmv_matches_oracle(D, O, transpose):
 @pytest.mark.parametrize("maker", [lpgen.config0,
                                    lambda: lpgen.huge_share_lp(m=2000, n=4000, seed=9),
                                    lambda: lpgen.transport_lp(40, 60, seed=3)])
-def test_sigma_max_matches_dense_two_norm(D, O, maker):
+@pytest.mark.parametrize("slices", [-1, 8])
+def test_sigma_max_matches_dense_two_norm(D, O, maker, slices):
     """The Lanczos estimate of sigma_max(A~) against the 2-norm of the
     oracle's scaled matrix (dense SVD).  It is a lower bound (up to rounding)
     within 1e-5 (the step size keeps a 2e-3 margin; the scaled matrices
@@ -136,7 +140,7 @@ def test_sigma_max_matches_dense_two_norm(D, O, maker):
     nearly orthogonal to the top singular vector), and at least as close as
     the oracle's power-iteration estimate."""
     lp = maker()
-    G = D.Problem(lp)
+    G = D.Problem(lp, gpu_params(D, gather_slices=slices))
     P = O.Problem(lp)
     s = G.scaling()
     assert abs(s["omega0"] - P.omega0) <= 1e-12 * P.omega0
@@ -152,9 +156,12 @@ def test_sigma_max_matches_dense_two_norm(D, O, maker):
     assert 2 <= r["power_iters"] <= 600
 
 
-def test_kkt_matches_oracle(D, O):
+@pytest.mark.parametrize("slices", [-1, 8])
+def test_kkt_matches_oracle(D, O, slices):
+    """KKT triple and objectives, unsliced and through the sliced check
+    passes (two-right-hand-side partials, combine with per-block sums)."""
     lp = lpgen.config0()
-    G = D.Problem(lp)
+    G = D.Problem(lp, gpu_params(D, gather_slices=slices))
     P = O.Problem(lp)
     k = G.kkt(lp.x_star, lp.y_star, tau=0.5)
     assert max(k[:3]) < 1e-13
