@@ -97,11 +97,14 @@ def step_of(name):
 def per_step_bytes(disp):
     """Mean KiB per launch of each fused FP64 step.  A step is the tile
     kernel and its split-segment fix-up or, in the XCD-sliced form, the
-    per-slice partial kernels, their fix-up and the combine kernel."""
+    per-slice partial kernel (and fix-up) and the combine kernel that follows
+    it; partial kernels followed by another pass's combine are dropped."""
     tot, launches, pending = defaultdict(float), defaultdict(int), 0.0
     for _, name, v in disp:
         s = step_of(name)
         if s is None:
+            if "k_combine<" in name:      # partial sums of another pass (checks, SpMV, Lanczos)
+                pending = 0.0
             continue
         if s == "partial":
             pending += v
