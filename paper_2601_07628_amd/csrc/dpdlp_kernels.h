@@ -132,12 +132,12 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op0, const Tile *__restrict_
     __shared__ double s_red[NQ][kBlock / 64];
     __shared__ AT s_redp[NR][kBlock / 64];
 
+    Op op = op0;
+    op.resolve();             // graph replays: its scalar loads go out with the tile's
     const int t = blk2tile ? blk2tile[blockIdx.x] : tile_of_block(remap);
     if (t < 0 || t >= ntiles) return;
     const Tile d = tiles[t];
-    Op op = op0;
     op.slice = d.slice;
-    op.resolve();
     seg_ptr += (size_t)d.slice * seg_stride;
     const int nnz0 = d.nnz_begin;
     const int cnt = d.nnz_end - d.nnz_begin;
