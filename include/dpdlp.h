@@ -94,7 +94,8 @@ typedef struct dpdlp_params {
     int32_t tile_nnz;         /* nonzeros per workgroup tile (Sec. 4.3 at CU */
                               /* granularity), max 2048; 0 = automatic: the  */
                               /* power of two in [256, 2048] nearest above   */
-                              /* nnz / 2048 (about 8 tiles per CU)           */
+                              /* nnz / 1280 (one round of 5 resident         */
+                              /* workgroups on each of the 256 CUs)          */
     uint64_t perm_seed;       /* seed of the block permutation               */
     int32_t precision;        /* DPDLP_FP64 or DPDLP_FP32_MIXED              */
     int32_t xcd_remap;        /* 1: map consecutive tiles onto one XCD        */

@@ -987,9 +987,11 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     std::unique_ptr<dpdlp_problem> guard(P);
     if (params) P->prm = *params; else dpdlp_params_default(&P->prm);
     if (P->prm.tile_nnz <= 0) {
-        // automatic: enough tiles for ~8 workgroups per CU (256 CUs), 256..2048
+        // automatic: the smallest power of two (256..2048) that keeps the
+        // tiles within one round of resident workgroups (256 CUs x 5), so
+        // that a small problem's tiles all run at once
         const int64_t nz = lp.row_ptr[lp.m];
-        int64_t tn = nz / (256 * 8);
+        int64_t tn = nz / (256 * 5);
         int32_t p2 = 256;
         while (p2 < tn && p2 < kTileNnzMax) p2 <<= 1;
         P->prm.tile_nnz = p2;
