@@ -326,7 +326,7 @@ struct TileSet {
     int nsplit = 0;
     int *blk2tile = nullptr;        // sliced sets: workgroup -> tile (-1: idle)
     int grid = 0;                   // sliced sets: launch size
-    int seg_stride = 0;             // per-slice pointer stride (0: one pointer array)
+    int seg_stride = 0;             // per-slice pointer stride (0 for the compact sliced form)
 };
 
 // One format cut into gather slices (the XCD-sliced form of a fused step).
@@ -390,7 +390,7 @@ struct dpdlp_problem {
     double *xbest = nullptr, *ybest = nullptr;  // T(z) of the FP32 phase's best check
     // scratch
     double *tmp_m = nullptr, *tmp_n = nullptr, *tmp_m2 = nullptr, *tmp_n2 = nullptr;
-    double *scal = nullptr;         // device scalars: [0] lam, [4..7] norms
+    double *scal = nullptr;         // device scalars: [4..7] norms, [8] beta, [9] alpha (Lanczos)
     double *norm_part = nullptr;
     double *sig_hist = nullptr;
     Control *ctl = nullptr;
