@@ -357,6 +357,14 @@ int dpdlp_block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t
 int dpdlp_build_tiles(const int32_t *seg_ptr, int32_t nseg, int32_t tile_nnz,
                       int32_t *tiles, int32_t *ntiles);
 
+/* Row bounds of the problem statement's Ax (=, >=, <=) b form (Sec. 2):
+ * row_type[i] 0 '=' gives lo = hi = b[i]; 1 '>=' gives lo = b[i], hi = +inf;
+ * 2 '<=' gives lo = -inf, hi = b[i].  Host arrays of length m, written into
+ * the caller's con_lo / con_hi.  INVALID_ARG for NULL pointers, m < 0, an
+ * unknown type or a non-finite b[i] (nothing is written then).            */
+int dpdlp_row_bounds(int32_t m, const double *b, const int32_t *row_type, double *con_lo,
+                     double *con_hi);
+
 /* Messages. */
 const char *dpdlp_status_string(int32_t status);
 const char *dpdlp_last_error(void);

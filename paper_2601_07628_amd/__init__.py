@@ -101,7 +101,7 @@ EXPORTS = (
     "dpdlp_state_export", "dpdlp_state_import", "dpdlp_get_log", "dpdlp_spmv",
     "dpdlp_kkt", "dpdlp_get_scaling", "dpdlp_time_kernel",
     "dpdlp_profile_enable", "dpdlp_get_profile", "dpdlp_validate",
-    "dpdlp_block_permutation", "dpdlp_build_tiles", "dpdlp_status_string",
+    "dpdlp_block_permutation", "dpdlp_build_tiles", "dpdlp_row_bounds", "dpdlp_status_string",
     "dpdlp_last_error", "dpdlp_gnn_create", "dpdlp_gnn_destroy", "dpdlp_gnn_num_params",
     "dpdlp_gnn_set_params", "dpdlp_gnn_get_params", "dpdlp_gnn_set_reference",
     "dpdlp_gnn_set_instance", "dpdlp_gnn_forward", "dpdlp_gnn_backward",
@@ -137,6 +137,7 @@ def _load():
         "dpdlp_get_profile": ([vp, vp, vp, vp], C.c_int),
         "dpdlp_validate": ([C.POINTER(CsrLP)], C.c_int),
         "dpdlp_block_permutation": ([i32, i32, u64, vp], C.c_int),
+        "dpdlp_row_bounds": ([i32, vp, vp, vp, vp], C.c_int),
         "dpdlp_build_tiles": ([vp, i32, i32, vp, C.POINTER(i32)], C.c_int),
         "dpdlp_status_string": ([i32], C.c_char_p),
         "dpdlp_gnn_create": ([vp, i32, vp, C.POINTER(vp)], C.c_int),
@@ -235,6 +236,17 @@ def dpdlp_block_permutation(count: int, block: int, seed: int) -> np.ndarray:
     perm = np.zeros(max(count, 1), np.int32)
     _check(_lib.dpdlp_block_permutation(count, block, seed, _ptr(perm)))
     return perm[:count]
+
+
+def dpdlp_row_bounds(b, row_type):
+    """(con_lo, con_hi) for rows given as b and types 0 '=', 1 '>=', 2 '<='."""
+    b = np.ascontiguousarray(b, np.float64)
+    t = np.ascontiguousarray(row_type, np.int32)
+    if b.shape != t.shape:
+        raise ValueError("b and row_type differ in length")
+    lo, hi = np.empty_like(b), np.empty_like(b)
+    _check(_lib.dpdlp_row_bounds(b.size, _ptr(b), _ptr(t), _ptr(lo), _ptr(hi)))
+    return lo, hi
 
 
 def dpdlp_build_tiles(seg_ptr, tile_nnz: int = 0) -> np.ndarray:

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <thread>
 #include <vector>
@@ -438,6 +439,31 @@ int dpdlp_validate(const dpdlp_csr_lp *lp)
         return DPDLP_E_INVALID_ARG;
     }
     return validate_host(lp);
+}
+
+int dpdlp_row_bounds(int32_t m, const double *b, const int32_t *row_type, double *con_lo,
+                     double *con_hi)
+{
+    if (m < 0 || (m > 0 && (!b || !row_type || !con_lo || !con_hi))) {
+        set_error("dpdlp_row_bounds: bad arguments");
+        return DPDLP_E_INVALID_ARG;
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        if (row_type[i] < 0 || row_type[i] > 2) {
+            set_error("dpdlp_row_bounds: row type must be 0 (=), 1 (>=) or 2 (<=)");
+            return DPDLP_E_INVALID_ARG;
+        }
+        if (!std::isfinite(b[i])) {
+            set_error("dpdlp_row_bounds: right-hand side must be finite");
+            return DPDLP_E_INVALID_ARG;
+        }
+    }
+    const double inf = std::numeric_limits<double>::infinity();
+    for (int32_t i = 0; i < m; ++i) {
+        con_lo[i] = row_type[i] == 2 ? -inf : b[i];
+        con_hi[i] = row_type[i] == 1 ? inf : b[i];
+    }
+    return DPDLP_OK;
 }
 
 int dpdlp_block_permutation(int32_t count, int32_t block, uint64_t seed, int32_t *perm)

@@ -168,3 +168,16 @@ def test_host_cpp_checks(tmp_path, prog):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout[-2000:] + out.stderr[-2000:]
     assert out.stdout.strip().endswith("ok")
+
+
+def test_row_bounds_from_row_types(D):
+    """Ax (=, >=, <=) b rows as [lo, hi] bounds; bad input is rejected."""
+    b = np.array([1.5, -2.0, 3.0, 0.0])
+    lo, hi = D.dpdlp_row_bounds(b, [0, 1, 2, 1])
+    assert np.array_equal(lo, [1.5, -2.0, -np.inf, 0.0])
+    assert np.array_equal(hi, [1.5, np.inf, 3.0, np.inf])
+    assert D.dpdlp_validate(lpgen.from_dense(np.eye(4), np.ones(4), lo, hi, np.zeros(4), np.ones(4))) == 0
+    with pytest.raises(D.DpdlpError, match="row type"):
+        D.dpdlp_row_bounds(b, [0, 1, 3, 1])
+    with pytest.raises(D.DpdlpError, match="finite"):
+        D.dpdlp_row_bounds([np.inf], [1])
