@@ -408,6 +408,17 @@ def test_bad_input_is_rejected_on_gpu(D):
     assert e.value.code == D.E_BAD_CSR
 
 
+@pytest.mark.parametrize("kw,msg", [(dict(gather_slices=12), "gather_slices"),
+                                    (dict(gather_slices=72), "gather_slices"),
+                                    (dict(perm_order=-1), "perm_order")])
+def test_bad_parameters_are_rejected(D, kw, msg):
+    """Slice counts that are not a multiple of 8 up to 64, and unknown
+    orders, are errors with a message (nothing is allocated)."""
+    with pytest.raises(D.DpdlpError, match=msg) as e:
+        D.Problem(lpgen.config0(), gpu_params(D, **kw))
+    assert e.value.code == D.E_INVALID_ARG
+
+
 @pytest.mark.parametrize("kw", [dict(), dict(precision=1), dict(gather_slices=8)])
 def test_graph_replay_matches_eager_bitwise(D, kw):
     """Runs between checks replayed as one HIP graph give bitwise the same
