@@ -413,7 +413,7 @@ def test_bad_input_is_rejected_on_gpu(D):
                                     (dict(perm_order=-1), "perm_order")])
 def test_bad_parameters_are_rejected(D, kw, msg):
     """Slice counts that are not a multiple of 8 up to 64, and unknown
-    orders, are errors with a message (nothing is allocated)."""
+    orders, are errors with a message; the partly built handle is freed."""
     with pytest.raises(D.DpdlpError, match=msg) as e:
         D.Problem(lpgen.config0(), gpu_params(D, **kw))
     assert e.value.code == D.E_INVALID_ARG
