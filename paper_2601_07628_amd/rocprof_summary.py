@@ -2,7 +2,7 @@
 
     python -m paper_2601_07628_amd.rocprof_summary trace  <kernel_stats.csv>
     python -m paper_2601_07628_amd.rocprof_summary traffic <fetch_counter.csv> <write_counter.csv> \
-        --out profiles/traffic.json --workload c1
+        --out profiles/c1_fused_steps_traffic.json --workload c1
     python -m paper_2601_07628_amd.rocprof_summary l2 <tcc_hit_miss_counter.csv>
 
 `trace` prints a per-kernel table (calls, mean/min/max duration); `l2`
