@@ -19,6 +19,12 @@
 // reduces its part and publishes it, and a small follow-up kernel adds the
 // pieces in piece order and runs the epilogue.  The summation order is fixed
 // by the tiling alone, so results are bitwise reproducible run to run.
+//
+// The XCD-sliced form (the paper's 2-D partition, Sec. 3.1 / App. D, across
+// the 8 XCDs): the gathered dimension is cut into S slices, slice s runs on
+// XCD s % 8 so its share of the gathered vector stays in that XCD's L2;
+// PartialOp writes one sum per (segment, slice) pair that has nonzeros, and
+// k_combine adds a segment's slice sums in slice order before the epilogue.
 #pragma once
 #include <hip/hip_runtime.h>
 
