@@ -434,3 +434,30 @@ def test_graph_replay_matches_eager_bitwise(D, kw):
     assert r0["status"] == 1 and r0["iters"] == r1["iters"]
     assert np.array_equal(r0["x"], r1["x"]) and np.array_equal(r0["y"], r1["y"])
     assert [e["restart"] for e in l0] == [e["restart"] for e in l1]
+
+
+@pytest.mark.parametrize("name,maker", [
+    ("c0", lpgen.config0),
+    ("huge-share-small", lambda: lpgen.huge_share_lp(m=20000, n=40000, seed=9)),
+    ("transport-60x4000", lambda: lpgen.transport_lp(60, 4000, seed=3))])
+def test_fp32_mixed_iterates_against_fp64_oracle(D, O, name, maker):
+    """The FP32-mixed form's error against the FP64 oracle after 64
+    iterations from the same start with the same step sizes (one epoch, the
+    same restart decision): FP32 rounding of A~, the iterates and the
+    accumulations, about 6e-8 per operation, keeps the iterates within 1e-5
+    relative.  The measured error is printed."""
+    lp = maker()
+    P0 = O.Problem(lp)
+    eta, w0 = P0.eta, P0.omega0
+    P = O.Problem(lp, oracle_params(O, eta=eta, omega0=w0, eps=0.0))
+    st = P.init_state()
+    P.run(st, 64)
+    G = D.Problem(lp, gpu_params(D, eta=eta, omega0=w0, eps=0.0, precision=D.FP32_MIXED,
+                                 fp32_switch_tol=0.0, fp32_stall_checks=10**6, fp32_diverge=0.0))
+    G.init()
+    G.iterate(64)
+    gs = G.state()
+    assert [e["restart"] for e in G.log()] == [e["restart"] for e in st["log"]]
+    errs = {k: rel(gs[k], st[k]) for k in ("xh", "yh")}
+    print(f"{name}: FP32-mixed vs FP64 oracle after 64 iterations: {errs}")
+    assert max(errs.values()) <= 1e-5, errs
