@@ -252,70 +252,71 @@ void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
     const int64_t nnz = ptr[(size_t)nseg];
     const int32_t planes = S / 8;
     const int32_t nblk = (nseg + kBlock - 1) / kBlock;
-    const int nth = std::min(S, host_threads());
-    // 1. per (slice, segment) counts; slice s is counted by thread s % nth
+    // threads own ranges of whole segments; every pass below is O(nnz + S nseg)
+    const int nth = host_threads();
+    std::vector<int32_t> g0v((size_t)nth + 1);
+    for (int t = 0; t <= nth; ++t) g0v[(size_t)t] = (int32_t)((int64_t)nseg * t / nth);
+    // 1. per (slice, segment) counts and per (thread, slice) totals
     hvec<int32_t> cnt((size_t)S * (size_t)nseg);      // every entry written below
-    std::vector<int64_t> gs((size_t)S, 0), zs((size_t)S, 0);
+    std::vector<int64_t> tg((size_t)nth * S, 0), tz((size_t)nth * S, 0);
     run_threads(nth, [&](int t) {
-        for (int32_t s = t; s < S; s += nth) {
-            const int32_t lo = s * size, hi = std::min(nidx, lo + size);
-            int32_t *c = cnt.data() + (size_t)s * nseg;
-            int64_t G = 0, Z = 0;
-            for (int32_t g = 0; g < nseg; ++g) {
-                int32_t k = 0;
-                for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p)
-                    k += (idx[(size_t)p] >= lo && idx[(size_t)p] < hi);
-                c[g] = k;
-                G += k > 0;
-                Z += k;
+        std::vector<int32_t> c((size_t)S);
+        for (int32_t g = g0v[(size_t)t]; g < g0v[(size_t)t + 1]; ++g) {
+            std::fill(c.begin(), c.end(), 0);
+            for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) c[(size_t)(idx[(size_t)p] / size)]++;
+            for (int32_t s = 0; s < S; ++s) {
+                cnt[(size_t)s * nseg + g] = c[(size_t)s];
+                tg[(size_t)t * S + s] += c[(size_t)s] > 0;
+                tz[(size_t)t * S + s] += c[(size_t)s];
             }
-            gs[(size_t)s] = G;
-            zs[(size_t)s] = Z;
         }
     });
-    // 2. compact numbering: slice-major, increasing segment within a slice
+    // 2. compact numbering: slice-major, increasing segment within a slice;
+    //    each thread's first compact segment and nonzero position per slice
     out.seg_base.assign((size_t)S + 1, 0);
     std::vector<int64_t> nz_base((size_t)S + 1, 0);
     for (int32_t s = 0; s < S; ++s) {
-        out.seg_base[(size_t)s + 1] = out.seg_base[(size_t)s] + (int32_t)gs[(size_t)s];
-        nz_base[(size_t)s + 1] = nz_base[(size_t)s] + zs[(size_t)s];
+        int64_t G = 0, Z = 0;
+        for (int t = 0; t < nth; ++t) { G += tg[(size_t)t * S + s]; Z += tz[(size_t)t * S + s]; }
+        out.seg_base[(size_t)s + 1] = out.seg_base[(size_t)s] + (int32_t)G;
+        nz_base[(size_t)s + 1] = nz_base[(size_t)s] + Z;
+    }
+    std::vector<int64_t> tq((size_t)nth * S), tp((size_t)nth * S);
+    for (int32_t s = 0; s < S; ++s) {
+        int64_t q = out.seg_base[(size_t)s], z = nz_base[(size_t)s];
+        for (int t = 0; t < nth; ++t) {
+            tq[(size_t)t * S + s] = q;
+            tp[(size_t)t * S + s] = z;
+            q += tg[(size_t)t * S + s];
+            z += tz[(size_t)t * S + s];
+        }
     }
     const int64_t G = out.seg_base[(size_t)S];
     out.G = G;
     out.ptr.resize((size_t)G + 1);          // every entry written below
     out.ptr[(size_t)G] = (int32_t)nnz;
     out.cbase.assign((size_t)nblk * (size_t)S, 0);
+    out.mask.assign((size_t)planes * (size_t)nseg, 0);
     out.idx.resize((size_t)nnz);
     out.src.resize((size_t)nnz);
+    // 3. pointers, combine bases, masks and the scatter, per segment range
     run_threads(nth, [&](int t) {
-        for (int32_t s = t; s < S; s += nth) {
-            const int32_t lo = s * size, hi = std::min(nidx, lo + size);
-            const int32_t *c = cnt.data() + (size_t)s * nseg;
-            int64_t q = out.seg_base[(size_t)s], pos = nz_base[(size_t)s];
-            for (int32_t g = 0; g < nseg; ++g) {
-                if (g % kBlock == 0) out.cbase[(size_t)(g / kBlock) * S + s] = (int32_t)q;
-                if (c[g] == 0) continue;
-                out.ptr[(size_t)q++] = (int32_t)pos;
-                for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
-                    const int32_t j = idx[(size_t)p];
-                    if (j < lo || j >= hi) continue;
-                    out.idx[(size_t)pos] = j;
-                    out.src[(size_t)pos] = p;
-                    ++pos;
+        std::vector<int64_t> q(tq.begin() + (size_t)t * S, tq.begin() + (size_t)(t + 1) * S);
+        std::vector<int64_t> z(tp.begin() + (size_t)t * S, tp.begin() + (size_t)(t + 1) * S);
+        for (int32_t g = g0v[(size_t)t]; g < g0v[(size_t)t + 1]; ++g) {
+            for (int32_t s = 0; s < S; ++s) {
+                if (g % kBlock == 0) out.cbase[(size_t)(g / kBlock) * S + s] = (int32_t)q[(size_t)s];
+                if (cnt[(size_t)s * nseg + g] > 0) {
+                    out.ptr[(size_t)q[(size_t)s]++] = (int32_t)z[(size_t)s];
+                    out.mask[(size_t)(s / 8) * nseg + g] |= (uint8_t)(1u << (s % 8));
                 }
             }
-        }
-    });
-    // 3. slice masks, S / 8 byte planes
-    out.mask.assign((size_t)planes * (size_t)nseg, 0);
-    run_threads(host_threads(), [&](int t) {
-        const int nt = host_threads();
-        const int32_t g0 = (int32_t)((int64_t)nseg * t / nt), g1 = (int32_t)((int64_t)nseg * (t + 1) / nt);
-        for (int32_t s = 0; s < S; ++s) {
-            const int32_t *c = cnt.data() + (size_t)s * nseg;
-            uint8_t *mk = out.mask.data() + (size_t)(s / 8) * nseg;
-            for (int32_t g = g0; g < g1; ++g)
-                if (c[g] > 0) mk[g] |= (uint8_t)(1u << (s % 8));
+            for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
+                const int32_t s = idx[(size_t)p] / size;
+                const int64_t at = z[(size_t)s]++;
+                out.idx[(size_t)at] = idx[(size_t)p];
+                out.src[(size_t)at] = p;
+            }
         }
     });
     // 4. tiles per slice over its compact segments (global segment numbers)
