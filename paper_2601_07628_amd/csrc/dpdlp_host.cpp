@@ -391,37 +391,68 @@ void permute_and_transpose(const dpdlp_csr_lp *lp, int32_t block, uint64_t seed,
     }
     for (auto &t : th) t.join();
 
-    // CSC by counting, prefix sum and a stable scatter (row order kept);
-    // thread t owns a range of columns and scans all rows in order.
-    H.cp.assign((size_t)n + 1, 0);
+    // CSC by a stable two-level bucket sort (row order kept inside every
+    // column).  Thread t owns rows [r_t, r_t+1) and column range c_t:
+    // A. each thread counts its nonzeros per column range;
+    // B. each thread copies (row, position) of its nonzeros into the column
+    //    range's bucket, rows in order, after the earlier threads' part;
+    // C. each thread counts, prefix-sums and scatters its own bucket.
     const int nct = host_threads();
-    auto crange = [&](int t, int32_t &c0, int32_t &c1) {
-        c0 = (int32_t)((int64_t)n * t / nct);
-        c1 = (int32_t)((int64_t)n * (t + 1) / nct);
+    std::vector<int32_t> c0v((size_t)nct + 1), r0v((size_t)nct + 1);
+    for (int t = 0; t <= nct; ++t) {
+        c0v[(size_t)t] = (int32_t)((int64_t)n * t / nct);
+        r0v[(size_t)t] = (int32_t)((int64_t)m * t / nct);
+    }
+    // owner of column j: the t with c0v[t] <= j < c0v[t+1]
+    auto owner = [&](int32_t j) {
+        int t = (int)((int64_t)j * nct / n);
+        while (t + 1 < nct && j >= c0v[(size_t)t + 1]) ++t;
+        while (t > 0 && j < c0v[(size_t)t]) --t;
+        return t;
     };
+    std::vector<int64_t> bc((size_t)nct * nct, 0);          // [row thread][bucket]
     run_threads(nct, [&](int t) {
-        int32_t c0, c1;
-        crange(t, c0, c1);
-        for (int64_t p = 0; p < H.nnz; ++p) {
-            const int32_t j = H.ci[(size_t)p];
-            if (j >= c0 && j < c1) H.cp[(size_t)j + 1]++;
-        }
+        int64_t *c = bc.data() + (size_t)t * nct;
+        for (int64_t p = H.rp[(size_t)r0v[(size_t)t]]; p < H.rp[(size_t)r0v[(size_t)t + 1]]; ++p)
+            c[owner(H.ci[(size_t)p])]++;
     });
-    for (int32_t j = 0; j < n; ++j) H.cp[(size_t)j + 1] += H.cp[(size_t)j];
-    std::vector<int32_t> next(H.cp.begin(), H.cp.end() - 1);
+    std::vector<int64_t> boff((size_t)nct * nct), bstart((size_t)nct + 1, 0);
+    for (int b = 0; b < nct; ++b) {
+        int64_t o = bstart[(size_t)b];
+        for (int t = 0; t < nct; ++t) {
+            boff[(size_t)t * nct + b] = o;
+            o += bc[(size_t)t * nct + b];
+        }
+        bstart[(size_t)b + 1] = o;
+    }
+    hvec<int32_t> brow((size_t)H.nnz), bpos((size_t)H.nnz);
+    run_threads(nct, [&](int t) {
+        std::vector<int64_t> o(boff.begin() + (size_t)t * nct, boff.begin() + (size_t)(t + 1) * nct);
+        for (int32_t i = r0v[(size_t)t]; i < r0v[(size_t)t + 1]; ++i)
+            for (int32_t p = H.rp[(size_t)i]; p < H.rp[(size_t)i + 1]; ++p) {
+                const int64_t q = o[(size_t)owner(H.ci[(size_t)p])]++;
+                brow[(size_t)q] = i;
+                bpos[(size_t)q] = p;
+            }
+    });
+    H.cp.assign((size_t)n + 1, 0);
     H.ri.resize((size_t)H.nnz);
     H.vt.resize((size_t)H.nnz);
-    run_threads(nct, [&](int t) {
-        int32_t c0, c1;
-        crange(t, c0, c1);
-        for (int32_t i = 0; i < m; ++i)
-            for (int32_t p = H.rp[(size_t)i]; p < H.rp[(size_t)i + 1]; ++p) {
-                const int32_t j = H.ci[(size_t)p];
-                if (j < c0 || j >= c1) continue;
-                const int32_t q = next[(size_t)j]++;
-                H.ri[(size_t)q] = i;
-                H.vt[(size_t)q] = H.v[(size_t)p];
-            }
+    run_threads(nct, [&](int b) {
+        for (int64_t q = bstart[(size_t)b]; q < bstart[(size_t)b + 1]; ++q)
+            H.cp[(size_t)H.ci[(size_t)bpos[(size_t)q]] + 1]++;
+    });
+    for (int32_t j = 0; j < n; ++j) H.cp[(size_t)j + 1] += H.cp[(size_t)j];
+    run_threads(nct, [&](int b) {
+        std::vector<int32_t> next(H.cp.begin() + c0v[(size_t)b], H.cp.begin() + c0v[(size_t)b + 1]);
+        const int32_t cb = c0v[(size_t)b];
+        for (int64_t q = bstart[(size_t)b]; q < bstart[(size_t)b + 1]; ++q) {
+            const int32_t p = bpos[(size_t)q];
+            const int32_t j = H.ci[(size_t)p];
+            const int32_t at = next[(size_t)(j - cb)]++;
+            H.ri[(size_t)at] = brow[(size_t)q];
+            H.vt[(size_t)at] = H.v[(size_t)p];
+        }
     });
 }
 
