@@ -867,7 +867,7 @@ static int lanczos_sigma(dpdlp_problem *P, uint64_t seed, int max_steps, double 
 // sigma_max(A~): the larger of two Lanczos estimates from independent
 // starts (a start nearly orthogonal to the top singular vector can settle
 // on the second singular value).
-static int power_iteration(dpdlp_problem *P)
+static int estimate_sigma_max(dpdlp_problem *P)
 {
     double s1 = 0, s2 = 0;
     int k1 = 0, k2 = 0;
@@ -1150,7 +1150,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         P->sigma_max = 0;
         P->power_iters = 0;
     } else {
-        CHK(power_iteration(P));
+        CHK(estimate_sigma_max(P));
         P->eta = P->sigma_max > 0 ? P->prm.eta_safety / P->sigma_max : 1.0;
     }
     // FP32 copies for the mixed-precision form
