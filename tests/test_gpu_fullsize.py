@@ -59,5 +59,12 @@ def test_c1_fullsize_parity(D, slices):
     _fullsize(D, lpgen.config1(), 3, slices)
 
 
+def test_c1_fullsize_two_check_blocks_with_graph_replay(D):
+    """140 iterations of c1 in the default configuration: checks at t = 0,
+    63 and 127, and iterations 64..126 replayed as one HIP graph; every output
+    and the restart log against the oracle."""
+    _fullsize(D, lpgen.config1(), 140, -1)
+
+
 def test_c2_fullsize_parity(D):
     _fullsize(D, lpgen.config2(), 3)
