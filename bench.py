@@ -189,7 +189,7 @@ def main():
                          "known size that calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
               "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
@@ -273,8 +273,8 @@ def main():
     del G
 
     def sliced(S):
-        # S = 0: no slicing; S = 8: both steps sliced (the default slices only
-        # where it pays)
+        # S = 0: no slicing; S = 8: both steps cut into 8 slices (the default
+        # chooses per step)
         GS = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9, gather_slices=S),
                        stream=stream)
         GS.init()
