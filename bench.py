@@ -167,6 +167,88 @@ def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3, eps_lis
     return out
 
 
+def layout_stats(D, lp, block, seed, tile_nnz=2048):
+    """Host statistics of the layout one permutation gives (Sec. 4.2-4.3 at
+    CU and XCD granularity): per-tile nonzero imbalance (max / mean) of the
+    nonzero-aware tiles the library builds and of uniform tiles (the same
+    number of tiles, equal segment counts), and, for the XCD-sliced form,
+    the nonzero share of the busiest XCD (slice s runs on XCD s mod 8)
+    relative to an even 1/8, for 8 and 16 slices of the gathered index range.
+    The compact (segment, slice) count decides whether the library slices a
+    step (20 bytes per compact segment against 12 per nonzero)."""
+    import numpy as np
+    m, n, nnz = lp.m, lp.n, lp.nnz
+    pr = D.dpdlp_block_permutation(m, block, seed)             # new row i = old pr[i]
+    pc = D.dpdlp_block_permutation(n, block, seed ^ 0xC01D5EED)
+    inv_r = np.empty(m, np.int64)
+    inv_r[pr] = np.arange(m)
+    inv_c = np.empty(n, np.int64)
+    inv_c[pc] = np.arange(n)
+    rows_old = np.repeat(np.arange(m, dtype=np.int64), np.diff(lp.row_ptr))
+    r_new = inv_r[rows_old]
+    del rows_old
+    c_new = inv_c[lp.col_idx]
+    rc = np.diff(lp.row_ptr)[pr]
+    cc = np.bincount(lp.col_idx, minlength=n)[pc]
+    out = {}
+    for name, counts, seg, idx, nidx in (("csr_dual", rc, r_new, c_new, n),
+                                         ("csc_primal", cc, c_new, r_new, m)):
+        ptr = np.zeros(counts.size + 1, np.int64)
+        np.cumsum(counts, out=ptr[1:])
+        t = D.dpdlp_build_tiles(ptr.astype(np.int32), tile_nnz)
+        tn = (t[:, 3] - t[:, 2]).astype(np.float64)
+        T = len(t)
+        b = (np.arange(T + 1, dtype=np.int64) * counts.size) // T
+        un = np.diff(ptr[b]).astype(np.float64)
+        e = {"tiles": T, "nnz_aware_max_over_mean": round(float(tn.max() / tn.mean()), 3),
+             "uniform_max_over_mean": round(float(un.max() / un.mean()), 3)}
+        for S in (8, 16):
+            size = (nidx + S - 1) // S
+            sl = idx // size
+            per_x = np.bincount(sl % 8, minlength=8)
+            G = int(np.count_nonzero(np.bincount(seg * S + sl, minlength=counts.size * S)))
+            e[f"S{S}"] = {"busiest_xcd_share_x8": round(float(per_x.max() * 8 / nnz), 3),
+                          "compact_segments": G,
+                          "slices_pay": bool(20.0 * G < 12.0 * nnz)}
+        out[name] = e
+    return out
+
+
+def ablation(D, torch, stream, steps, ips):
+    """Permutation x partition ablation at CU/XCD granularity (Sec. 4.2-4.3)
+    on config 1 (heavy rows clustered in the first 10%) and its staircase
+    variant: no permutation, a full random permutation (blocks of 1) and the
+    block-wise random permutation (B = 256), each with the automatic and with
+    no XCD slicing; FP64 iterations/s and the fused steps' launch times."""
+    import lpgen
+    seed = D.dpdlp_params_default().perm_seed
+    res = {}
+    for lname, mk in (("c1", lpgen.config1), ("staircase", lpgen.config1_staircase)):
+        lp = mk()
+        log(f"ablation: {lname} {lp.describe()}")
+        for block in (0, 1, 256):
+            key = f"{lname}/perm_block={block}"
+            res[key] = {"layout": layout_stats(D, lp, block, seed)}
+            for S in (-1, 0):
+                G = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9, perm_block=block,
+                                             gather_slices=S), stream=stream)
+                G.init()
+                G.iterate(2 * ips)
+                G.profile_enable(True)
+                el = timed_steps(G, steps, ips, torch)
+                p = G.profile()
+                r = G.result(want_xy=False)
+                ms = {k: round(p[k]["total_ms"] / max(p[k]["launches"], 1), 4)
+                      for k in ("primal", "dual")}
+                res[key]["slices_auto" if S < 0 else "slices_off"] = {
+                    "iters_per_s": round(steps * ips / el, 1), "primal_ms": ms["primal"],
+                    "dual_ms": ms["dual"], "setup_s": round(r["setup_seconds"], 3)}
+                log(f"ablation {key} gather_slices={S}: {res[key]}")
+                G.close()
+        del lp
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +269,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 256 MiB buffer (device to device), a kernel of "
                          "known size that calibrates the HBM byte counters")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the benchmark, run the permutation x partition "
+                         "ablation on config 1 and its staircase variant")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
@@ -201,6 +286,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    if args.ablation:
+        res = ablation(D, torch, stream, args.steps, args.iters_per_step)
+        print(json.dumps({"ablation": "permutation x partition (FP64, PDHG iters/s)",
+                          "steps": args.steps, "iters_per_step": args.iters_per_step,
+                          "kernel_source": kernel_source_hash(), "results": res}), flush=True)
+        return
 
     if args.calib_copy:
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")

@@ -243,6 +243,69 @@ def config1() -> LP:
     return _cached("c1", lambda: huge_share_lp(seed=1, name="c1"))
 
 
+def staircase_lp(m: int = 2_000_000, n: int = 4_000_000, stages: int = 2000,
+                 per_col: int = 10, link: float = 0.3, seed: int = 5,
+                 name: str = "staircase") -> LP:
+    """Multi-period (staircase) LP of config-1 size with a constructed optimum.
+
+    Rows and columns are cut into ``stages`` contiguous stages.  Each column
+    holds ``per_col`` distinct rows; each row is drawn uniformly from its own
+    stage, or with probability ``link`` from the next stage (the linking
+    constraints of a multi-period model; the last stage links to itself).
+    In the natural order every column's rows lie in two consecutive stages,
+    so the gathers of both products are local.  Values are N(0,1); half the
+    rows are '=', half '>='.
+    """
+    rng = np.random.default_rng(seed)
+    if per_col > m // stages:
+        raise ValueError("per_col exceeds the rows of a stage")
+    r_lo = (np.arange(stages + 1, dtype=np.int64) * m) // stages
+    c_stage = (np.arange(n, dtype=np.int64) * stages) // n
+    col_of = np.repeat(np.arange(n, dtype=np.int64), per_col)
+
+    def draw(cols):
+        s = c_stage[cols]
+        nxt = rng.random(cols.size) < link
+        s = np.where(nxt, np.minimum(s + 1, stages - 1), s)
+        return r_lo[s] + (rng.random(cols.size) * (r_lo[s + 1] - r_lo[s])).astype(np.int64)
+
+    cols, rows = col_of, draw(col_of)
+    for _ in range(64):
+        key = cols * m + rows
+        order = np.argsort(key, kind="stable")
+        key, rows, cols = key[order], rows[order], cols[order]
+        dup = np.zeros(key.size, dtype=bool)
+        dup[1:] = key[1:] == key[:-1]
+        if not dup.any():
+            break
+        rows[dup] = draw(cols[dup])
+    else:
+        raise RuntimeError("could not make rows distinct inside columns")
+    counts = np.bincount(rows, minlength=m)
+    empty = np.flatnonzero(counts == 0)
+    if empty.size:
+        # an empty row takes one entry in a random column of its stage
+        st = np.searchsorted(r_lo, empty, side="right") - 1
+        c_lo = (st * n + stages - 1) // stages
+        c_hi = ((st + 1) * n + stages - 1) // stages
+        extra = c_lo + (rng.random(empty.size) * (c_hi - c_lo)).astype(np.int64)
+        rows = np.concatenate([rows, empty])
+        cols = np.concatenate([cols, extra])
+    vals = rng.standard_normal(rows.size)
+    row_ptr, col_idx, val = _csr_from_coo(m, n, rows, cols, vals)
+    del rows, cols, vals
+    A = sp.csr_matrix((val, col_idx, row_ptr), shape=(m, n))
+    x_star, y_star, con_lo, con_hi, c = _construct_optimum(rng, A, m // 2, 10.0)
+    return LP(m, n, row_ptr, col_idx, val, c, con_lo, con_hi,
+              np.zeros(n), np.full(n, 10.0), name=name, x_star=x_star,
+              y_star=y_star, obj_star=float(c @ x_star))
+
+
+def config1_staircase() -> LP:
+    """The staircase variant of config 1 (same m, n and nonzeros per column)."""
+    return _cached("staircase", lambda: staircase_lp(seed=5))
+
+
 def transport_lp(n_src: int = 3000, n_dst: int = 3000, seed: int = 2,
                  name: str = "c2") -> LP:
     """Transportation LP: supply rows '<=' then demand rows '>='.

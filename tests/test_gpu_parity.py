@@ -225,6 +225,24 @@ def test_hot_first_order_skewed_lp(D, O, order, slices):
     fixed_run(D, O, lp, 200, gpu_kw=dict(perm_order=order, gather_slices=slices))
 
 
+@pytest.mark.parametrize("block,slices", [(1, -1), (1, 16), (0, 8), (0, 16)])
+def test_permutation_variants_skewed_lp(D, O, block, slices):
+    """A full random permutation (blocks of 1) and no permutation, with XCD
+    slicing, on a config-1 shaped LP at 1/40 scale: without a permutation
+    the heavy rows fill the first slice of y.  Only the summation order
+    changes."""
+    lp = lpgen.huge_share_lp(50000, 100000, seed=11)
+    fixed_run(D, O, lp, 200, gpu_kw=dict(perm_block=block, gather_slices=slices))
+
+
+@pytest.mark.parametrize("block", [0, 1, 256])
+def test_permutation_variants_staircase_lp(D, O, block):
+    """The staircase LP (local gathers in the natural order) under each
+    permutation, sliced into 8."""
+    lp = lpgen.staircase_lp(20000, 40000, stages=40, per_col=10, seed=3)
+    fixed_run(D, O, lp, 200, gpu_kw=dict(perm_block=block, gather_slices=8))
+
+
 def test_perm_order_rejects_unknown(D):
     with pytest.raises(RuntimeError, match="perm_order"):
         D.Problem(lpgen.config0(), gpu_params(D, perm_order=4))

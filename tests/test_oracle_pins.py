@@ -185,6 +185,22 @@ def test_kkt_zero_at_constructed_optimum(oracle_mod, tau):
     assert np.isclose(k[4], bty, rtol=1e-12)
 
 
+def test_staircase_generator_structure_and_optimum(oracle_mod):
+    """The staircase variant of config 1 (at 1/100 scale): every column's
+    rows lie in its own stage or the next one, no row is empty, and the
+    constructed optimum has zero KKT residuals with c^T x* = b^T y*."""
+    lp = lpgen.staircase_lp(20000, 40000, stages=40, per_col=10, seed=3)
+    A = lp.scipy_csr().tocoo()
+    d = (A.row * 40) // lp.m - (A.col * 40) // lp.n
+    assert set(np.unique(d).tolist()) <= {0, 1}
+    assert np.all(np.diff(lp.row_ptr) > 0)
+    assert np.all(np.bincount(lp.col_idx, minlength=lp.n) >= 10)
+    k = oracle_mod.Problem(lp).kkt(lp.x_star, lp.y_star, tau=1.0)
+    assert max(k[0], k[1], k[2]) < 1e-13
+    assert np.isclose(k[4], lp.con_lo @ lp.y_star, rtol=1e-12)
+    assert np.isclose(k[3], k[4], rtol=1e-10)
+
+
 def test_kkt_at_highs_optimum_and_objective(oracle_mod):
     """HiGHS's primal/dual pair (converted to this sign convention) has tiny
     KKT residuals in the oracle's measure, and the oracle solve reaches the
