@@ -365,6 +365,53 @@ int dpdlp_build_tiles(const int32_t *seg_ptr, int32_t nseg, int32_t tile_nnz,
 int dpdlp_row_bounds(int32_t m, const double *b, const int32_t *row_type, double *con_lo,
                      double *con_hi);
 
+/* ---- cost model of the distributed method (host only) ------------------- */
+
+/* Constants of the per-iteration cost model (Sec. 3.3; App. E.1 and E.3):
+ * bandwidths in bytes/s, latency in seconds, traffic coefficients in bytes. */
+typedef struct dpdlp_cost_params {
+    double b_mem;             /* effective HBM bandwidth of one device       */
+    double b_net;             /* effective interconnect bandwidth            */
+    double beta_sync;         /* latency of one single-hop collective        */
+    double n_hop;             /* mean hop count between devices              */
+    double c_spmv;            /* bytes per nonzero per iteration (24: FP64   */
+                              /* value + INT32 index, read in CSR and CSC)   */
+    double c_vec;             /* bytes per vector element per iteration (90) */
+    double c_net;             /* bytes per all-reduced element (8, FP64)     */
+} dpdlp_cost_params;
+
+/* MI355X defaults: b_mem 8.0e12 (HBM3E peak), b_net 153.6e9 (one xGMI link:
+ * a ring moves over one link per hop), beta_sync 10e-6 and n_hop 1 (the
+ * paper's single-node values), c_spmv 24, c_vec 90, c_net 8.               */
+void dpdlp_cost_params_default(dpdlp_cost_params *p);
+
+/* Modelled time of one iteration on an R x C device grid (Sec. 3.3, the
+ * four terms derived in App. E.2), in seconds: out[0] matrix stream
+ * c_spmv nnz / (b_mem R C); out[1] vector traffic c_vec (n/C + m/R) / b_mem;
+ * out[2] ring all-reduce payload c_net (n R + m C - (m + n)) / (R C b_net);
+ * out[3] latency n_hop beta_sync ([R > 1] + [C > 1]); out[4] the sum.
+ * out has room for 5 doubles.  INVALID_ARG for negative sizes, R or C < 1,
+ * NULL pointers, or non-positive / non-finite bandwidths.                 */
+int dpdlp_cost_step(int64_t m, int64_t n, int64_t nnz, int32_t R, int32_t C,
+                    const dpdlp_cost_params *p, double *out);
+
+/* Grid for ndev devices (Sec. 4.1): the factor pair R x C = ndev whose
+ * aspect ratio R / C is closest to m / n, closeness measured as a ratio,
+ * |log(R/C) - log(m/n)| (the reading that reproduces every grid of the
+ * worked examples in App. E.4); ties (equal up to 1e-12) take the
+ * smaller R.  INVALID_ARG for
+ * m, n or ndev < 1 or NULL outputs.                                       */
+int dpdlp_grid_select(int64_t m, int64_t n, int32_t ndev, int32_t *R, int32_t *C);
+
+/* Automatic device count (Sec. 5.1): for each candidate count (counts,
+ * ncounts > 0, e.g. {1, 2, 4, 8}) take its grid from dpdlp_grid_select and
+ * its modelled time from dpdlp_cost_step; return the count with the least
+ * time (ties: the smaller count), its grid, and that time in *t_step (may
+ * be NULL).  INVALID_ARG for bad sizes, a count < 1 or NULL outputs.       */
+int dpdlp_auto_devices(int64_t m, int64_t n, int64_t nnz, const int32_t *counts,
+                       int32_t ncounts, const dpdlp_cost_params *p, int32_t *ndev,
+                       int32_t *R, int32_t *C, double *t_step);
+
 /* Messages. */
 const char *dpdlp_status_string(int32_t status);
 const char *dpdlp_last_error(void);

@@ -93,6 +93,15 @@ class LogRec(C.Structure):
                 ("omega", C.c_double), ("restart", C.c_int32), ("pad", C.c_int32)]
 
 
+class CostParams(C.Structure):
+    _fields_ = [("b_mem", C.c_double), ("b_net", C.c_double), ("beta_sync", C.c_double),
+                ("n_hop", C.c_double), ("c_spmv", C.c_double), ("c_vec", C.c_double),
+                ("c_net", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # Every symbol include/dpdlp.h declares (checked by the CPU test suite).
 EXPORTS = (
     "dpdlp_params_default", "dpdlp_problem_create", "dpdlp_problem_destroy",
@@ -105,7 +114,8 @@ EXPORTS = (
     "dpdlp_last_error", "dpdlp_gnn_create", "dpdlp_gnn_destroy", "dpdlp_gnn_num_params",
     "dpdlp_gnn_set_params", "dpdlp_gnn_get_params", "dpdlp_gnn_set_reference",
     "dpdlp_gnn_set_instance", "dpdlp_gnn_forward", "dpdlp_gnn_backward",
-    "dpdlp_gnn_adam_step", "dpdlp_gnn_gemm_test",
+    "dpdlp_gnn_adam_step", "dpdlp_gnn_gemm_test", "dpdlp_cost_params_default",
+    "dpdlp_cost_step", "dpdlp_grid_select", "dpdlp_auto_devices",
 )
 
 
@@ -153,6 +163,11 @@ def _load():
         "dpdlp_gnn_gemm_test": ([vp, C.c_long, C.c_long, vp, C.c_long, C.c_long, vp, C.c_long,
                                  i32, i32, i32, vp], C.c_int),
         "dpdlp_last_error": ([], C.c_char_p),
+        "dpdlp_cost_params_default": ([C.POINTER(CostParams)], None),
+        "dpdlp_cost_step": ([i64, i64, i64, i32, i32, C.POINTER(CostParams), vp], C.c_int),
+        "dpdlp_grid_select": ([i64, i64, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
+        "dpdlp_auto_devices": ([i64, i64, i64, vp, i32, C.POINTER(CostParams), C.POINTER(i32),
+                                C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -259,6 +274,42 @@ def dpdlp_build_tiles(seg_ptr, tile_nnz: int = 0) -> np.ndarray:
     cnt2 = C.c_int32(cnt.value)
     _check(_lib.dpdlp_build_tiles(_ptr(sp_), sp_.size - 1, tile_nnz, _ptr(out), C.byref(cnt2)))
     return out[: cnt.value]
+
+
+def dpdlp_cost_params_default(**kw) -> CostParams:
+    p = CostParams()
+    _lib.dpdlp_cost_params_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def dpdlp_cost_step(m: int, n: int, nnz: int, R: int, C_: int,
+                    params: Optional[CostParams] = None) -> dict:
+    """Modelled seconds per iteration on an R x C grid, by term."""
+    p = params if params is not None else dpdlp_cost_params_default()
+    out = np.zeros(5)
+    _check(_lib.dpdlp_cost_step(m, n, nnz, R, C_, C.byref(p), _ptr(out)))
+    return dict(spmv=float(out[0]), vec=float(out[1]), net=float(out[2]),
+                sync=float(out[3]), total=float(out[4]))
+
+
+def dpdlp_grid_select(m: int, n: int, ndev: int):
+    r, c = C.c_int32(0), C.c_int32(0)
+    _check(_lib.dpdlp_grid_select(m, n, ndev, C.byref(r), C.byref(c)))
+    return r.value, c.value
+
+
+def dpdlp_auto_devices(m: int, n: int, nnz: int, counts=(1, 2, 4, 8),
+                       params: Optional[CostParams] = None) -> dict:
+    p = params if params is not None else dpdlp_cost_params_default()
+    cnt = np.ascontiguousarray(counts, np.int32)
+    nd, r, c, t = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_double(0.0)
+    _check(_lib.dpdlp_auto_devices(m, n, nnz, _ptr(cnt), cnt.size, C.byref(p), C.byref(nd),
+                                   C.byref(r), C.byref(c), C.byref(t)))
+    return dict(ndev=nd.value, R=r.value, C=c.value, t_step=t.value)
 
 
 def dpdlp_problem_create(lp, params: Optional[Params] = None, stream=None,
