@@ -109,17 +109,21 @@ typedef struct dpdlp_params {
                               /* phase's best one with its primal weight    */
     int32_t gather_slices;    /* -1 (default): automatic; 0: off; S (multiple */
                               /* of 8, <= 64): cut the gathered dimension of */
-                              /* each fused step into S slices, slice s on   */
-                              /* XCD s % 8, partial sums added per segment in */
-                              /* slice order (the 2-D partition of Sec. 3.1  */
-                              /* across the 8 XCDs).  Automatic slices a step */
-                              /* when its gathered vector exceeds 4 MB and   */
-                              /* its partial sums, one per (segment, slice)  */
-                              /* with nonzeros at 20 bytes each, cost less   */
-                              /* than its 12 bytes per nonzero: S = 16 when  */
-                              /* 8 slices would exceed 2 MB each (in the     */
-                              /* iterate's precision) and each gathered      */
-                              /* element is read >= 4 times per pass, else 8 */
+                              /* each fused step into S contiguous slices of */
+                              /* equal nonzero counts, slice s on XCD s % 8, */
+                              /* partial sums added per segment in slice     */
+                              /* order (the 2-D partition of Sec. 3.1 across */
+                              /* the 8 XCDs).  Automatic slices a step when  */
+                              /* its gathered vector exceeds 4 MB, when the  */
+                              /* gathers of one XCD's resident tiles (160    */
+                              /* consecutive tiles) touch more than 2 MB of  */
+                              /* it, and when its partial sums, one per      */
+                              /* (segment, slice) with nonzeros at 20 bytes  */
+                              /* each, cost less than its 12 bytes per       */
+                              /* nonzero: S = 16 when 8 slices would exceed  */
+                              /* 2 MB each (in the iterate's precision) and  */
+                              /* each gathered element is read >= 4 times    */
+                              /* per pass, else 8                            */
     int32_t use_graphs;       /* 1: replay the check_period - 1 iterations    */
                               /* between two checks as one HIP graph (off    */
                               /* while dpdlp_profile_enable is on)           */

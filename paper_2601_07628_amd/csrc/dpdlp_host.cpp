@@ -221,10 +221,65 @@ void build_tiles(const int32_t *ptr, int32_t nseg, int32_t tile_nnz,
     }
 }
 
-int64_t count_compact(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
-                      int32_t nseg, int32_t nidx, int32_t S)
+void slice_bounds(const hvec<int32_t> &gptr, int32_t nidx, int32_t S,
+                  std::vector<int32_t> &bounds)
 {
-    const int32_t size = (nidx + S - 1) / S;
+    // slice s starts at the first index whose prefix count reaches s nnz / S;
+    // whatever the order of the indices, every slice (and so every XCD) gets
+    // about the same number of gathers, and under a random order the ranges
+    // come out close to equal
+    const int64_t nnz = gptr[(size_t)nidx];
+    bounds.assign((size_t)S + 1, 0);
+    bounds[(size_t)S] = nidx;
+    for (int32_t s = 1; s < S; ++s) {
+        const int64_t target = nnz * s / S;
+        const int32_t b = (int32_t)(std::lower_bound(gptr.begin(), gptr.begin() + (size_t)nidx + 1,
+                                                     target,
+                                                     [](int32_t v, int64_t t) { return (int64_t)v < t; }) -
+                                    gptr.begin());
+        bounds[(size_t)s] = std::min(std::max(b, bounds[(size_t)s - 1]), nidx);
+    }
+}
+
+// slice of every gathered index
+static void slice_map(const std::vector<int32_t> &bounds, int32_t nidx, int32_t S, hvec<uint8_t> &map)
+{
+    map.resize((size_t)nidx);
+    for (int32_t s = 0; s < S; ++s)
+        std::fill(map.begin() + bounds[(size_t)s], map.begin() + bounds[(size_t)s + 1], (uint8_t)s);
+}
+
+double gather_window_bytes(const hvec<int32_t> &idx, int64_t nnz, int32_t nidx, int64_t window,
+                           int32_t line_elems, int nsample)
+{
+    if (nnz <= 0 || nidx <= 0 || nsample <= 0) return 0.0;
+    window = std::max<int64_t>(1, std::min(window, nnz));
+    const int64_t nlines = ((int64_t)nidx + line_elems - 1) / line_elems;
+    std::vector<uint64_t> bits((size_t)((nlines + 63) / 64), 0);
+    std::vector<double> fp((size_t)nsample);
+    for (int k = 0; k < nsample; ++k) {
+        const int64_t a = nsample > 1 ? (nnz - window) * k / (nsample - 1) : 0;
+        int64_t cnt = 0;
+        for (int64_t p = a; p < a + window; ++p) {
+            const int64_t l = idx[(size_t)p] / line_elems;
+            uint64_t &w = bits[(size_t)(l >> 6)];
+            const uint64_t b = 1ull << (l & 63);
+            if (!(w & b)) { w |= b; ++cnt; }
+        }
+        for (int64_t p = a; p < a + window; ++p) bits[(size_t)((idx[(size_t)p] / line_elems) >> 6)] = 0;
+        fp[(size_t)k] = 128.0 * (double)cnt;
+    }
+    std::nth_element(fp.begin(), fp.begin() + nsample / 2, fp.end());
+    return fp[(size_t)nsample / 2];
+}
+
+int64_t count_compact(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
+                      const hvec<int32_t> &gptr, int32_t nseg, int32_t nidx, int32_t S)
+{
+    std::vector<int32_t> bounds;
+    slice_bounds(gptr, nidx, S, bounds);
+    hvec<uint8_t> smap;
+    slice_map(bounds, nidx, S, smap);
     const int nth = host_threads();
     std::vector<int64_t> part((size_t)nth, 0);
     run_threads(nth, [&](int t) {
@@ -233,7 +288,7 @@ int64_t count_compact(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
         int64_t G = 0;
         for (int32_t g = g0; g < g1; ++g)
             for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
-                const int32_t s = idx[(size_t)p] / size;
+                const int32_t s = smap[(size_t)idx[(size_t)p]];
                 if (last[(size_t)s] != g) { last[(size_t)s] = g; ++G; }
             }
         part[(size_t)t] = G;
@@ -243,12 +298,13 @@ int64_t count_compact(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
     return G;
 }
 
-void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
+void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx, const hvec<int32_t> &gptr,
                   int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out)
 {
     out.S = S;
-    out.size = (nidx + S - 1) / S;
-    const int32_t size = out.size;
+    slice_bounds(gptr, nidx, S, out.bounds);
+    hvec<uint8_t> smap;
+    slice_map(out.bounds, nidx, S, smap);
     const int64_t nnz = ptr[(size_t)nseg];
     const int32_t planes = S / 8;
     const int32_t nblk = (nseg + kBlock - 1) / kBlock;
@@ -263,7 +319,7 @@ void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
         std::vector<int32_t> c((size_t)S);
         for (int32_t g = g0v[(size_t)t]; g < g0v[(size_t)t + 1]; ++g) {
             std::fill(c.begin(), c.end(), 0);
-            for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) c[(size_t)(idx[(size_t)p] / size)]++;
+            for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) c[(size_t)smap[(size_t)idx[(size_t)p]]]++;
             for (int32_t s = 0; s < S; ++s) {
                 cnt[(size_t)s * nseg + g] = c[(size_t)s];
                 tg[(size_t)t * S + s] += c[(size_t)s] > 0;
@@ -312,7 +368,7 @@ void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
                 }
             }
             for (int32_t p = ptr[(size_t)g]; p < ptr[(size_t)g + 1]; ++p) {
-                const int32_t s = idx[(size_t)p] / size;
+                const int32_t s = smap[(size_t)idx[(size_t)p]];
                 const int64_t at = z[(size_t)s]++;
                 out.idx[(size_t)at] = idx[(size_t)p];
                 out.src[(size_t)at] = p;

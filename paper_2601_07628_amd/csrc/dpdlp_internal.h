@@ -44,18 +44,29 @@ template <class T> using hvec = std::vector<T, NoInitAlloc<T>>;
 // cbase[q * S + s] is the compact index of the first segment of slice s at
 // or after original segment q * kBlock.  Tiles carry their slice.
 struct SlicedHost {
-    int32_t S = 0, size = 0;
+    int32_t S = 0;
+    std::vector<int32_t> bounds;     // slice s gathers indices [bounds[s], bounds[s+1])
     int64_t G = 0;
     hvec<int32_t> ptr, idx, src;
     std::vector<int32_t> seg_base, cbase;
     std::vector<uint8_t> mask;
     std::vector<Tile> tiles;
 };
-void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
+// Slices are S contiguous ranges of the gathered index that hold about
+// nnz / S nonzeros each; gptr[nidx + 1] is the gathered dimension's own
+// pointer array (its nonzero counts as prefix sums).
+void slice_bounds(const hvec<int32_t> &gptr, int32_t nidx, int32_t S,
+                  std::vector<int32_t> &bounds);
+void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx, const hvec<int32_t> &gptr,
                   int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out);
 // Number of compact segments (segment, slice) with a nonzero, for S slices.
 int64_t count_compact(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
-                      int32_t nseg, int32_t nidx, int32_t S);
+                      const hvec<int32_t> &gptr, int32_t nseg, int32_t nidx, int32_t S);
+// Bytes of the gathered vector (distinct 128-byte lines of line_elems
+// indices) touched by `window` consecutive nonzeros in storage order: the
+// median over nsample windows spread over the matrix.
+double gather_window_bytes(const hvec<int32_t> &idx, int64_t nnz, int32_t nidx, int64_t window,
+                           int32_t line_elems, int nsample);
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 #ifndef DPDLP_TILE_NNZ_MAX

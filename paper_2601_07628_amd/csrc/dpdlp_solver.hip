@@ -746,13 +746,14 @@ static int build_tileset(dpdlp_problem *P, const hvec<int32_t> &ptr, int32_t nse
 }
 
 // Sliced copy of one format: tiles of slice s run on XCD s % 8 (workgroup b
-// runs on XCD b % 8), the slices of one XCD one after another.
+// runs on XCD b % 8), the slices of one XCD one after another.  gptr is the
+// gathered dimension's pointer array (slices hold equal nonzero counts).
 static int build_sliced(dpdlp_problem *P, const hvec<int32_t> &ptr,
-                        const hvec<int32_t> &idx, int32_t nseg, int32_t nidx, int S,
-                        SlicedSet &ss)
+                        const hvec<int32_t> &idx, const hvec<int32_t> &gptr, int32_t nseg,
+                        int32_t nidx, int S, SlicedSet &ss)
 {
     SlicedHost sh;
-    slice_format(ptr, idx, nseg, nidx, S, P->prm.tile_nnz, sh);
+    slice_format(ptr, idx, gptr, nseg, nidx, S, P->prm.tile_nnz, sh);
     ss.S = S;
     const size_t nnz = sh.idx.size();
     CHK(dalloc(P, &ss.ptr, sh.ptr.size()));
@@ -1029,14 +1030,17 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     CHK(build_tileset(P, H.cp, n, P->tc, ht));
     int ntmax = std::max(P->tr.n, P->tc.n);
     // XCD-sliced fused steps: S > 0 slices both steps; S < 0 (automatic)
-    // slices a step when its gathered vector exceeds one XCD's L2 (4 MB) and
-    // its compact partial sums (written and read, 8 + 8 bytes, plus a 4-byte
+    // slices a step when its gathered vector exceeds one XCD's L2 (4 MB),
+    // when the gathers of one XCD's resident tiles (5 workgroups on each of
+    // its 32 CUs, a contiguous run of tiles) touch more than half an L2 of
+    // it (so the order gives them no locality of their own), and when its
+    // compact partial sums (written and read, 8 + 8 bytes, plus a 4-byte
     // pointer per compact segment) cost less than its matrix stream (12
-    // bytes per nonzero), with S = 16 where 8 slices would still leave more
+    // bytes per nonzero); with S = 16 where 8 slices would still leave more
     // than 2 MB per slice (in the iterate's precision) of a vector that is
-    // gathered at least 4 times per pass, else S = 8; never when the gathered dimension
-    // is in hot-first order (equal index ranges would put most nonzeros in
-    // one slice, and the order itself gives the cache locality).
+    // gathered at least 4 times per pass, else S = 8; never when the
+    // gathered dimension is in hot-first order (the order itself gives the
+    // cache locality).
     int Sd = 0, Sp = 0;                 // dual (CSR, gathers x), primal (CSC, gathers y)
     if (P->prm.gather_slices > 0) {
         if (P->prm.gather_slices % 8 != 0 || P->prm.gather_slices > 64) {
@@ -1048,21 +1052,24 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         const double mat = 12.0 * (double)nnz, l2 = 4.0 * (1 << 20);
         const double eb = P->prm.precision == DPDLP_FP32_MIXED ? 4.0 : 8.0;   // gathered element
         const bool hot_rows = P->prm.perm_order & 1, hot_cols = P->prm.perm_order & 2;
-        auto pick = [&](const hvec<int32_t> &ptr, const hvec<int32_t> &idx, int32_t nseg,
-                        int32_t nidx) -> int {
+        auto pick = [&](const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
+                        const hvec<int32_t> &gptr, int32_t nseg, int32_t nidx) -> int {
             if (8.0 * nidx <= l2) return 0;
+            const int64_t window = (int64_t)32 * 5 * P->prm.tile_nnz;
+            if (gather_window_bytes(idx, nnz, nidx, window, (int32_t)(128 / eb), 16) <= l2 / 2)
+                return 0;
             // 16 slices when 8 would leave more than half an L2 per slice and
             // each gathered element is read at least 4 times per pass
             int S = (eb * nidx / 8.0 > l2 / 2 && (double)nnz >= 4.0 * nidx) ? 16 : 8;
             for (; S >= 8; S /= 2)
-                if (20.0 * (double)count_compact(ptr, idx, nseg, nidx, S) < mat) return S;
+                if (20.0 * (double)count_compact(ptr, idx, gptr, nseg, nidx, S) < mat) return S;
             return 0;
         };
-        if (!hot_cols) Sd = pick(H.rp, H.ci, m, n);
-        if (!hot_rows) Sp = pick(H.cp, H.ri, n, m);
+        if (!hot_cols) Sd = pick(H.rp, H.ci, H.cp, m, n);
+        if (!hot_rows) Sp = pick(H.cp, H.ri, H.rp, n, m);
     }
-    if (Sd) CHK(build_sliced(P, H.rp, H.ci, m, n, Sd, P->sr));     // dual: gathers xbar
-    if (Sp) CHK(build_sliced(P, H.cp, H.ri, n, m, Sp, P->sc));     // primal: gathers y
+    if (Sd) CHK(build_sliced(P, H.rp, H.ci, H.cp, m, n, Sd, P->sr));   // dual: gathers xbar
+    if (Sp) CHK(build_sliced(P, H.cp, H.ri, H.rp, n, m, Sp, P->sc));   // primal: gathers y
     if (Sd || Sp) {
         ntmax = std::max(ntmax, std::max(P->sr.ts.n, P->sc.ts.n));
         // the sliced CSR check pass keeps two right-hand sides (2 G doubles)

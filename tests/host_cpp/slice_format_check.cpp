@@ -7,6 +7,10 @@
 //     their nonzero range matches the pointers;
 //   * every sliced nonzero lies in its slice's index range and src points
 //     back to the same index in the unsliced format;
+//   * the slice ranges tile [0, nidx) and hold equal nonzero counts up to
+//     one index's count (slice_bounds);
+//   * gather_window_bytes equals a brute-force count of distinct lines on
+//     single windows;
 //   * the combine's position rule (cbase of the 256-segment block plus the
 //     count of earlier segments of the block with that slice bit) stays in
 //     range and adds up to the unsliced segment sum.
@@ -41,13 +45,33 @@ int main()
             for (int c : cols) idx.push_back(c);
             ptr[(size_t)g + 1] = (int32_t)idx.size();
         }
+        // the gathered dimension's pointers (its nonzero counts as prefix sums)
+        hvec<int32_t> gptr((size_t)nidx + 1);
+        std::vector<int32_t> gcnt((size_t)nidx, 0);
+        for (int32_t c : idx) gcnt[(size_t)c]++;
+        gptr[0] = 0;
+        for (int i = 0; i < nidx; ++i) gptr[(size_t)i + 1] = gptr[(size_t)i] + gcnt[(size_t)i];
         std::vector<double> val(idx.size()), v((size_t)nidx);
         for (auto &a : val) a = (double)(rng() % 1000) / 7.0;
         for (auto &a : v) a = (double)(rng() % 1000) / 3.0;
         SlicedHost sh;
         const int tile = 64 << (rng() % 6);
-        slice_format(ptr, idx, nseg, nidx, S, tile, sh);
-        if (sh.G != count_compact(ptr, idx, nseg, nidx, S)) { std::printf("G mismatch\n"); ++bad; }
+        slice_format(ptr, idx, gptr, nseg, nidx, S, tile, sh);
+        if (sh.G != count_compact(ptr, idx, gptr, nseg, nidx, S)) { std::printf("G mismatch\n"); ++bad; }
+        if ((int)sh.bounds.size() != S + 1 || sh.bounds[0] != 0 || sh.bounds[(size_t)S] != nidx) {
+            std::printf("bounds ends\n");
+            ++bad;
+            continue;
+        }
+        {
+            const int64_t nz = (int64_t)idx.size();
+            const int32_t big = *std::max_element(gcnt.begin(), gcnt.end());
+            for (int s = 0; s < S; ++s) {
+                if (sh.bounds[(size_t)s] > sh.bounds[(size_t)s + 1]) { std::printf("bounds order\n"); ++bad; }
+                const int64_t in = gptr[(size_t)sh.bounds[(size_t)s + 1]] - gptr[(size_t)sh.bounds[(size_t)s]];
+                if (in > nz / S + 1 + big) { std::printf("slice %d holds %ld of %ld\n", s, (long)in, (long)nz); ++bad; }
+            }
+        }
         std::vector<int> cover((size_t)sh.G, 0);
         for (const Tile &t : sh.tiles) {
             if (t.seg_begin < sh.seg_base[(size_t)t.slice] || t.seg_end > sh.seg_base[(size_t)t.slice + 1]) {
@@ -67,7 +91,10 @@ int main()
         for (int s = 0; s < S; ++s)
             for (int64_t g = sh.seg_base[(size_t)s]; g < sh.seg_base[(size_t)s + 1]; ++g)
                 for (int p = sh.ptr[(size_t)g]; p < sh.ptr[(size_t)g + 1]; ++p) {
-                    if (sh.idx[(size_t)p] / sh.size != s) { std::printf("index outside slice\n"); ++bad; }
+                    if (sh.idx[(size_t)p] < sh.bounds[(size_t)s] || sh.idx[(size_t)p] >= sh.bounds[(size_t)s + 1]) {
+                        std::printf("index outside slice\n");
+                        ++bad;
+                    }
                     if (idx[(size_t)sh.src[(size_t)p]] != sh.idx[(size_t)p]) { std::printf("src\n"); ++bad; }
                     part[(size_t)g] += val[(size_t)sh.src[(size_t)p]] * v[(size_t)sh.idx[(size_t)p]];
                 }
@@ -91,6 +118,26 @@ int main()
                     ++bad;
                 }
             }
+    }
+    // gather_window_bytes: one window (nsample = 1 takes the first) against a
+    // brute-force set of lines, on random and on clustered indices
+    for (int trial = 0; trial < 20; ++trial) {
+        const int32_t nidx = 1 + (int32_t)(rng() % 100000);
+        const int64_t nnz = 1 + (int64_t)(rng() % 50000);
+        hvec<int32_t> idx((size_t)nnz);
+        const int32_t span = trial % 2 ? nidx : 1 + nidx / 50;
+        for (auto &x : idx) x = (int32_t)(rng() % (uint64_t)span);
+        const int64_t window = 1 + (int64_t)(rng() % (uint64_t)nnz);
+        const int32_t le = trial % 3 ? 16 : 32;
+        std::vector<char> seen((size_t)(nidx / le + 1), 0);
+        int64_t cnt = 0;
+        for (int64_t p = 0; p < window; ++p)
+            if (!seen[(size_t)(idx[(size_t)p] / le)]) { seen[(size_t)(idx[(size_t)p] / le)] = 1; ++cnt; }
+        const double got = gather_window_bytes(idx, nnz, nidx, window, le, 1);
+        if (got != 128.0 * (double)cnt) { std::printf("window %g vs %g\n", got, 128.0 * cnt); ++bad; }
+        // several windows: the median lies between the smallest and largest
+        const double med = gather_window_bytes(idx, nnz, nidx, window, le, 7);
+        if (med < 128.0 || med > 128.0 * (double)window) { std::printf("window median %g\n", med); ++bad; }
     }
     std::printf(bad ? "FAILED %d\n" : "ok\n", bad);
     return bad != 0;
