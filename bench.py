@@ -173,9 +173,11 @@ def layout_stats(D, lp, block, seed, tile_nnz=2048):
     nonzero-aware tiles the library builds and of uniform tiles (the same
     number of tiles, equal segment counts), and, for the XCD-sliced form,
     the nonzero share of the busiest XCD (slice s runs on XCD s mod 8)
-    relative to an even 1/8, for 8 and 16 slices of the gathered index range.
-    The compact (segment, slice) count decides whether the library slices a
-    step (20 bytes per compact segment against 12 per nonzero)."""
+    relative to an even 1/8, for 8 and 16 slices of the gathered index range,
+    cut into equal index ranges and into ranges of equal nonzero counts (the
+    library's slices).  The compact (segment, slice) count enters the
+    library's choice to slice a step (20 bytes per compact segment against
+    12 per nonzero)."""
     import numpy as np
     m, n, nnz = lp.m, lp.n, lp.nnz
     pr = D.dpdlp_block_permutation(m, block, seed)             # new row i = old pr[i]
@@ -191,8 +193,8 @@ def layout_stats(D, lp, block, seed, tile_nnz=2048):
     rc = np.diff(lp.row_ptr)[pr]
     cc = np.bincount(lp.col_idx, minlength=n)[pc]
     out = {}
-    for name, counts, seg, idx, nidx in (("csr_dual", rc, r_new, c_new, n),
-                                         ("csc_primal", cc, c_new, r_new, m)):
+    for name, counts, seg, idx, nidx, gcounts in (("csr_dual", rc, r_new, c_new, n, cc),
+                                                  ("csc_primal", cc, c_new, r_new, m, rc)):
         ptr = np.zeros(counts.size + 1, np.int64)
         np.cumsum(counts, out=ptr[1:])
         t = D.dpdlp_build_tiles(ptr.astype(np.int32), tile_nnz)
@@ -202,12 +204,16 @@ def layout_stats(D, lp, block, seed, tile_nnz=2048):
         un = np.diff(ptr[b]).astype(np.float64)
         e = {"tiles": T, "nnz_aware_max_over_mean": round(float(tn.max() / tn.mean()), 3),
              "uniform_max_over_mean": round(float(un.max() / un.mean()), 3)}
+        gpre = np.concatenate([[0], np.cumsum(gcounts)])
         for S in (8, 16):
             size = (nidx + S - 1) // S
-            sl = idx // size
+            per_eq = np.bincount((idx // size) % 8, minlength=8)
+            bnd = np.searchsorted(gpre, (nnz * np.arange(1, S)) // S, side="left")
+            sl = np.searchsorted(bnd, idx, side="right")
             per_x = np.bincount(sl % 8, minlength=8)
             G = int(np.count_nonzero(np.bincount(seg * S + sl, minlength=counts.size * S)))
             e[f"S{S}"] = {"busiest_xcd_share_x8": round(float(per_x.max() * 8 / nnz), 3),
+                          "busiest_xcd_share_x8_equal_ranges": round(float(per_eq.max() * 8 / nnz), 3),
                           "compact_segments": G,
                           "slices_pay": bool(20.0 * G < 12.0 * nnz)}
         out[name] = e
