@@ -23,6 +23,10 @@ in for them):
                  and ``config4_family(i)`` its perturbed family members.
 * ``tiny_lp``    dense tiny LPs (n<=6) with finite boxes and mixed row types,
                  for brute-force vertex enumeration.
+* ``staircase_lp`` the multi-period (staircase) variant of config 1.
+* ``constructed_qp`` / ``lasso_qp``  diagonal QPs (Sec. 6): a constructed
+                 optimum with c shifted by -Q x*, and the LASSO of App. J on a
+                 synthetic sparse feature matrix; ``LP.q`` holds diag(Q).
 
 The constructed-optimum recipe: x* has 60% of its entries in (0, 10) and the
 rest at 0; y* is N(0,1) on equality rows, |N(0,1)| on active '>=' rows and 0 on
@@ -58,7 +62,8 @@ class LP:
     name: str = ""
     x_star: Optional[np.ndarray] = None   # constructed primal optimum, if any
     y_star: Optional[np.ndarray] = None   # constructed dual optimum, if any
-    obj_star: Optional[float] = None      # c^T x* of the constructed optimum
+    obj_star: Optional[float] = None      # objective at the constructed optimum
+    q: Optional[np.ndarray] = None        # diagonal of Q for a QP (x^T Q x / 2), else None
 
     @property
     def nnz(self) -> int:
@@ -163,6 +168,75 @@ def constructed_lp(m: int, n: int, m_eq: int, per_col: int, seed: int,
     return LP(m, n, row_ptr, col_idx, val, c, con_lo, con_hi,
               np.zeros(n), np.full(n, x_hi), name=name, x_star=x_star,
               y_star=y_star, obj_star=float(c @ x_star))
+
+
+def constructed_qp(m: int, n: int, m_eq: int, per_col: int, seed: int,
+                   q_frac: float = 0.5, name: str = "constructed-qp") -> LP:
+    """Diagonal QP with a constructed optimum (Sec. 6): the config-0 recipe's
+    LP optimum (x*, y*) with Q_jj ~ U(0.1, 2) on a random q_frac of the
+    columns, and c shifted by -Q x*, so that c + Q x* - A^T y* is the LP's
+    reduced cost and (x*, y*) stays optimal."""
+    base = constructed_lp(m, n, m_eq, per_col, seed, name=name)
+    rng = np.random.default_rng(seed + 7919)
+    q = np.zeros(n)
+    on = rng.random(n) < q_frac
+    q[on] = rng.uniform(0.1, 2.0, size=int(on.sum()))
+    c = base.c - q * base.x_star
+    obj = float(c @ base.x_star + 0.5 * base.x_star @ (q * base.x_star))
+    return LP(base.m, base.n, base.row_ptr, base.col_idx, base.val, c, base.con_lo,
+              base.con_hi, base.var_lo, base.var_hi, name=name, x_star=base.x_star,
+              y_star=base.y_star, obj_star=obj, q=q)
+
+
+def lasso_qp(samples: int, features: int, per_row: int, seed: int,
+             lam_frac: float = 0.01, name: str = "lasso") -> LP:
+    """LASSO as a diagonal QP (App. J): min ||A x - b||^2 / 2 + lam ||x||_1
+    becomes min r^T r / 2 + lam 1^T t  s.t.  A x - r = b,  x - t <= 0,
+    x + t >= 0, over (x, r, t).  A synthetic sparse feature matrix stands in
+    for the LIBSVM data: each sample holds per_row features drawn with
+    Zipf-like popularity, values U(0, 1).  As in App. J the target b is the
+    last column of the matrix (the remaining columns are the features) and
+    lam = lam_frac ||A^T b||_inf.  Variables: x and r free, t >= 0.
+
+    Rows: samples '=' rows, then features '<=' rows (x - t), then features
+    '>=' rows (x + t); columns: x (features), r (samples), t (features)."""
+    rng = np.random.default_rng(seed)
+    nf = features + 1
+    w = 1.0 / np.arange(1, nf + 1) ** 0.8
+    w /= w.sum()
+    rows = np.repeat(np.arange(samples), per_row)
+    cols = rng.choice(nf, size=rows.size, p=w)
+    # the target column is present in about half of the samples
+    tgt = rng.random(samples) < 0.5
+    rows = np.concatenate([rows, np.flatnonzero(tgt)])
+    cols = np.concatenate([cols, np.full(int(tgt.sum()), nf - 1)])
+    key = np.unique(rows.astype(np.int64) * nf + cols)
+    rows, cols = key // nf, key % nf
+    vals = rng.uniform(0.0, 1.0, size=rows.size)
+    F = sp.csr_matrix((vals, (rows, cols)), shape=(samples, nf))
+    b = F[:, nf - 1].toarray().ravel()
+    A = F[:, : nf - 1].tocsr()
+    lam = lam_frac * float(np.max(np.abs(A.T @ b)))
+    n_x, n_r = features, samples
+    I_f = sp.identity(features, format="csr")
+    I_s = sp.identity(samples, format="csr")
+    Z_sf = sp.csr_matrix((samples, features))
+    top = sp.hstack([A, -I_s, Z_sf])
+    mid = sp.hstack([I_f, sp.csr_matrix((features, samples)), -I_f])
+    bot = sp.hstack([I_f, sp.csr_matrix((features, samples)), I_f])
+    M = sp.vstack([top, mid, bot]).tocsr()
+    M.sort_indices()
+    m_rows, n_cols = M.shape
+    con_lo = np.concatenate([b, np.full(features, -INF), np.zeros(features)])
+    con_hi = np.concatenate([b, np.zeros(features), np.full(features, INF)])
+    c = np.concatenate([np.zeros(n_x + n_r), np.full(features, lam)])
+    q = np.concatenate([np.zeros(n_x), np.ones(n_r), np.zeros(features)])
+    var_lo = np.concatenate([np.full(n_x + n_r, -INF), np.zeros(features)])
+    var_hi = np.full(n_cols, INF)
+    lp = LP(m_rows, n_cols, M.indptr.astype(np.int32), M.indices.astype(np.int32),
+            M.data.astype(np.float64), c, con_lo, con_hi, var_lo, var_hi, name=name, q=q)
+    lp.lasso = dict(A=A, b=b, lam=lam)
+    return lp
 
 
 def config0() -> LP:

@@ -127,6 +127,8 @@ def lib():
         L.ora_run.restype = i64
         L.ora_unscale.argtypes = [vp, vp, vp, vp, vp]
         L.ora_csr_to_csc.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
+        L.ora_set_qdiag.argtypes = [vp, vp]
+        L.ora_set_qdiag.restype = C.c_int
         L.ora_num_threads.restype = i32
         _lib = L
     return _lib
@@ -158,9 +160,12 @@ def csr_to_csc(m, n, row_ptr, col_idx, val):
 
 
 class Problem:
-    """A prepared problem: CSC built, rescaled, eta and omega0 chosen."""
+    """A prepared problem: CSC built, rescaled, eta and omega0 chosen.
 
-    def __init__(self, lp, params: Params | None = None):
+    A diagonal quadratic objective x^T Q x / 2 (Sec. 6) comes from ``q``
+    (length n, >= 0), else from ``lp.q`` when the instance carries one."""
+
+    def __init__(self, lp, params: Params | None = None, q=None):
         self.params = params or Params()
         self.m, self.n = int(lp.m), int(lp.n)
         self._keep = [np.ascontiguousarray(lp.row_ptr, np.int32),
@@ -179,6 +184,12 @@ class Problem:
         self.eta, self.omega0, self.sigma_max = out6[0], out6[1], out6[2]
         self.c_norm, self.b_norm = out6[3], out6[4]
         self.power_iters = int(iout[0])
+        if q is None:
+            q = getattr(lp, "q", None)
+        self.q = None if q is None else _f64(q)
+        if self.q is not None:
+            assert self.q.shape == (self.n,) and np.all(self.q >= 0)
+            lib().ora_set_qdiag(self._h, _p(self.q))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -22,6 +22,11 @@
  *                  r^2 expanded as in App. D.2.1.
  *   primal weight  App. B.3 (PID on log(omega ||dx|| / ||dy||)), App. D.2.2.
  *   KKT            App. B.4 (relative primal / dual residuals and gap).
+ *   diagonal QP    Sec. 6: objective c^T x + x^T Q x / 2 with Q diagonal; the
+ *                  primal step minimises over the box per column (closed
+ *                  form), the KKT adds Q x to the dual residual and
+ *                  x^T Q x / 2 to the primal and subtracts it from the dual
+ *                  objective (the Wolfe dual of the QP).
  *
  * Steps the paper leaves open, and the readings taken here:
  *   - Lagrangian sign: L(x,y) = c^T x - y^T A x - p(-y; l_c, u_c).  This is the
@@ -108,6 +113,7 @@ typedef struct {
     double c_norm_s, b_norm_s;      /* the same on the scaled problem       */
     double sigma_max, eta, omega0;
     int32_t power_iters;
+    double *q;                      /* scaled diagonal of Q (NULL: an LP)    */
 } ora_prob;
 
 static double clampd(double v, double lo, double hi)
@@ -331,7 +337,7 @@ void ora_free(ora_prob *P)
     if (!P) return;
     void *ptrs[] = {P->rp, P->ci, P->v, P->cp, P->ri, P->vt, P->c, P->clo, P->chi,
                     P->vlo, P->vhi, P->c0, P->clo0, P->chi0, P->vlo0, P->vhi0,
-                    P->dr, P->dc};
+                    P->dr, P->dc, P->q};
     for (size_t q = 0; q < sizeof(ptrs) / sizeof(ptrs[0]); ++q) free(ptrs[q]);
     free(P);
 }
@@ -358,6 +364,19 @@ void ora_get_scaled(const ora_prob *P, double *v, double *vt, double *dr, double
     if (vhi) memcpy(vhi, P->vhi, sizeof(double) * (size_t)P->n);
 }
 
+/* Diagonal quadratic objective (Sec. 6): q[n] >= 0 in original columns, or
+ * NULL for an LP.  The scaled problem holds D_c Q D_c, so q~_j = dc_j^2 q_j;
+ * the step size and primal weight are those of the LP part.               */
+int ora_set_qdiag(ora_prob *P, const double *q)
+{
+    free(P->q);
+    P->q = NULL;
+    if (!q) return 0;
+    P->q = (double *)malloc(sizeof(double) * (size_t)(P->n > 0 ? P->n : 1));
+    for (int32_t j = 0; j < P->n; ++j) P->q[j] = P->dc[j] * P->dc[j] * q[j];
+    return 0;
+}
+
 /* Products with the scaled matrix (for tests). */
 void ora_spmv(const ora_prob *P, int32_t transpose, const double *in, double *out)
 {
@@ -381,13 +400,19 @@ static void pdhg_halpern(const ora_prob *P, const double *x, const double *y,
     int32_t m = P->m, n = P->n;
     double a = (double)(k + 1) / (double)(k + 2);
     double b = 1.0 / (double)(k + 2);
-    /* primal: xh = proj_X(x - tau (c - A^T y)), xbar = 2 xh - x */
+    /* primal: xh = proj_X(x - tau (c - A^T y)), xbar = 2 xh - x.  With a
+     * diagonal Q (Sec. 6) xh minimises q x^2 / 2 + (c - A^T y) x
+     * + (x - x_k)^2 / (2 tau) over the box, separately per column: the
+     * unconstrained minimiser (x_k - tau (c - A^T y)) / (1 + tau q) clamped
+     * into [l, u] (a convex one-dimensional quadratic). */
 #pragma omp parallel for schedule(static)
     for (int32_t j = 0; j < n; ++j) {
         double aty = 0.0;
         for (int64_t p = P->cp[j]; p < P->cp[j + 1]; ++p) aty += P->vt[p] * y[P->ri[p]];
         double g = P->c[j] - aty;
-        double xhj = clampd(x[j] - tau * g, P->vlo[j], P->vhi[j]);
+        double u = x[j] - tau * g;
+        if (P->q) u = u / (1.0 + tau * P->q[j]);
+        double xhj = clampd(u, P->vlo[j], P->vhi[j]);
         xh[j] = xhj;
         xb[j] = 2.0 * xhj - x[j];
     }
@@ -435,14 +460,18 @@ static void kkt_eval(const ora_prob *P, const double *xh, const double *yh, doub
         else if (yi < 0.0) py += P->chi0[i] * yi;
     }
     for (int32_t j = 0; j < n; ++j) {
-        double g = P->c[j] - aty[j];                   /* scaled c - A^T y  */
+        /* scaled c + Q x - A^T y; with D_c Q D_c the scaled Q, its term
+         * q~ x~ is D_c (Q x), and q~ x~^2 = x^T Q x per column */
+        double qx = P->q ? P->q[j] * xh[j] : 0.0;
+        double g = P->c[j] + qx - aty[j];
         double u = xh[j] - tau * g;
         double s = (clampd(u, P->vlo[j], P->vhi[j]) - u) / tau;
-        double dres_j = (g - s) / P->dc[j];            /* original c - A^T y - s */
+        double dres_j = (g - s) / P->dc[j];            /* original c + Qx - A^T y - s */
         dres += dres_j * dres_j;
         double xj = P->dc[j] * xh[j];                  /* original primal   */
-        cx += P->c0[j] * xj;
-        sx += (s / P->dc[j]) * xj;
+        double half_xqx = 0.5 * qx * xh[j];
+        cx += P->c0[j] * xj + half_xqx;                /* c^T x + x^T Q x / 2 */
+        sx += (s / P->dc[j]) * xj - half_xqx;          /* dual: - x^T Q x / 2 */
     }
     double dobj = py + sx;
     out[0] = sqrt(pres) / (1.0 + P->b_norm);

@@ -6,6 +6,8 @@ scipy's HiGHS, textbook special cases, library routines (scipy transpose,
 numpy 2-norm).  A plausible slip anywhere in the oracle (a dropped term, a
 sign, an index, a transposed operand) fails at least one of them.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -377,3 +379,98 @@ def test_thread_count_does_not_change_results(oracle_mod):
         env = dict(os.environ, OMP_NUM_THREADS=th)
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env))
     assert outs[0] == outs[1]
+
+
+# -- Sec. 6: diagonal QP ----------------------------------------------------------
+def test_qp_kkt_zero_at_constructed_optimum(oracle_mod):
+    """A constructed diagonal QP (the LP optimum with c shifted by -Q x*) has
+    zero KKT residuals at (x*, y*) and the objective c^T x* + x*^T Q x* / 2.
+    A dropped Q x term in the dual residual, or a missing half-quadratic in
+    either objective, leaves a residual or a gap here."""
+    lp = lpgen.constructed_qp(300, 500, 150, 4, seed=3)
+    P = oracle_mod.Problem(lp)
+    for tau in (1e-3, 0.5, 10.0):
+        k = P.kkt(lp.x_star, lp.y_star, tau=tau)
+        assert max(k[0], k[1], k[2]) < 1e-13, k
+        assert np.isclose(k[3], lp.obj_star, rtol=1e-13)
+        assert np.isclose(k[4], lp.obj_star, rtol=1e-11)
+    # without Q the same point is not optimal (its dual residual is Q x*)
+    k0 = oracle_mod.Problem(lp, q=np.zeros(lp.n)).kkt(lp.x_star, lp.y_star, tau=1.0)
+    assert k0[1] > 1e-3
+
+
+def test_qp_step_minimises_the_prox_subproblem(oracle_mod):
+    """The QP primal step (Sec. 6) is the minimiser over the box of
+    q x^2 / 2 + g x + (x - x_k)^2 / (2 tau), checked per column with scipy's
+    bounded scalar minimiser; with q = 0 it is the LP step bit for bit."""
+    from scipy.optimize import minimize_scalar
+    lp = lpgen.constructed_qp(40, 60, 20, 3, seed=5)
+    P = oracle_mod.Problem(lp)
+    P0 = oracle_mod.Problem(lp, q=np.zeros(lp.n))
+    PL = oracle_mod.Problem(dataclasses.replace(lp, q=None))
+    d = P.scaled()
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 3, lp.n) / d["dc"]
+    y = rng.standard_normal(lp.m)
+    tau, sigma = 0.37, 0.9
+    o = P.step(x, y, x, y, 0, tau, sigma)
+    A = sp.csr_matrix((d["v"], lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n))
+    g = d["c"] - A.T @ y
+    qs = d["dc"] ** 2 * lp.q
+    for j in range(lp.n):
+        f = lambda v: 0.5 * qs[j] * v * v + g[j] * v + (v - x[j]) ** 2 / (2 * tau)
+        r = minimize_scalar(f, bounds=(d["vlo"][j], d["vhi"][j]), method="bounded",
+                            options=dict(xatol=1e-12))
+        assert abs(o["xh"][j] - r.x) <= 1e-7 * (1 + abs(r.x)), j
+    o0, oL = P0.step(x, y, x, y, 0, tau, sigma), PL.step(x, y, x, y, 0, tau, sigma)
+    for k in ("xh", "yh", "xn", "yn"):
+        assert np.array_equal(o0[k], oL[k])
+
+
+def _lasso_cd(A, b, lam, sweeps=20000):
+    """Textbook cyclic coordinate descent for the LASSO (soft thresholding)."""
+    A = A.toarray()
+    n = A.shape[1]
+    x = np.zeros(n)
+    r = b.copy()
+    cs = (A * A).sum(axis=0)
+    for _ in range(sweeps):
+        big = 0.0
+        for j in range(n):
+            if cs[j] == 0.0:
+                continue
+            rho = A[:, j] @ r + cs[j] * x[j]
+            xn = np.sign(rho) * max(abs(rho) - lam, 0.0) / cs[j]
+            if xn != x[j]:
+                r += A[:, j] * (x[j] - xn)
+                big = max(big, abs(xn - x[j]))
+                x[j] = xn
+        if big < 1e-15:
+            break
+    return x
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_lasso_qp_matches_coordinate_descent(oracle_mod, seed):
+    """The LASSO of App. J as a diagonal QP, solved by the oracle to 1e-9,
+    against cyclic coordinate descent on the LASSO itself: the same LASSO
+    objective and the same x."""
+    lp = lpgen.lasso_qp(60, 25, 4, seed=seed)
+    A, b, lam = lp.lasso["A"], lp.lasso["b"], lp.lasso["lam"]
+    P = oracle_mod.Problem(lp, oracle_mod.Params(eps=1e-9))
+    r = P.solve(max_iters=2_000_000)
+    assert r["status"] == 1
+    nf = A.shape[1]
+    x = r["x"][:nf]
+    f = lambda v: 0.5 * float(np.sum((A @ v - b) ** 2)) + lam * float(np.abs(v).sum())
+    xc = _lasso_cd(A, b, lam)
+    assert abs(f(x) - f(xc)) <= 1e-7 * (1 + f(xc))
+    assert np.allclose(x, xc, atol=1e-5)
+    assert abs(r["obj_p"] - f(xc)) <= 1e-7 * (1 + f(xc))
+
+
+def test_constructed_qp_solves_to_its_optimum(oracle_mod):
+    lp = lpgen.constructed_qp(300, 500, 150, 4, seed=3)
+    r = oracle_mod.Problem(lp).solve(max_iters=300_000)
+    assert r["status"] == 1
+    assert abs(r["obj_p"] - lp.obj_star) <= 1e-7 * (1 + abs(lp.obj_star))
