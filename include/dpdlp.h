@@ -202,6 +202,22 @@ int dpdlp_problem_update_data(dpdlp_problem *prob, const double *c, const double
  * precision) are fixed at creation and ignored here.  Errors: INVALID_ARG. */
 int dpdlp_set_params(dpdlp_problem *prob, const dpdlp_params *params);
 
+/* Diagonal quadratic objective (Sec. 6): the problem becomes
+ *     min c^T x + x^T Q x / 2,  Q = diag(q),  under the same constraints.
+ * q[n] (host or device per mem_kind, original column order, every entry
+ * finite and >= 0) is copied; NULL returns to the LP.  The primal step
+ * becomes the closed-form minimiser over the box of the separable
+ * subproblem, xh = clamp((x - tau (c - A^T y)) / (1 + tau q), l, u) in the
+ * scaled space (scaled Q = D_c Q D_c); the KKT adds Q x to the dual
+ * residual, x^T Q x / 2 to the primal objective and takes it off the dual
+ * objective.  Scaling, step size and primal weight stay those of the LP
+ * part.  Call before dpdlp_init / dpdlp_solve (a later call takes effect
+ * from the next iteration).  FP64 only: NOT_SUPPORTED when the problem was
+ * created with DPDLP_FP32_MIXED.  INVALID_ARG for a negative or non-finite
+ * entry or a bad mem_kind.                                                */
+int dpdlp_set_objective_diag(dpdlp_problem *prob, const double *q, int32_t mem_kind,
+                             void *stream);
+
 /* Start from (x0, y0) (original space; NULL = zeros): the point is scaled,
  * clamped into X and projected onto Y, and becomes the epoch anchor.  The
  * pointers are host or device per mem_kind.                              */

@@ -115,7 +115,7 @@ EXPORTS = (
     "dpdlp_gnn_set_params", "dpdlp_gnn_get_params", "dpdlp_gnn_set_reference",
     "dpdlp_gnn_set_instance", "dpdlp_gnn_forward", "dpdlp_gnn_backward",
     "dpdlp_gnn_adam_step", "dpdlp_gnn_gemm_test", "dpdlp_cost_params_default",
-    "dpdlp_cost_step", "dpdlp_grid_select", "dpdlp_auto_devices",
+    "dpdlp_cost_step", "dpdlp_grid_select", "dpdlp_auto_devices", "dpdlp_set_objective_diag",
 )
 
 
@@ -163,6 +163,7 @@ def _load():
         "dpdlp_gnn_gemm_test": ([vp, C.c_long, C.c_long, vp, C.c_long, C.c_long, vp, C.c_long,
                                  i32, i32, i32, vp], C.c_int),
         "dpdlp_last_error": ([], C.c_char_p),
+        "dpdlp_set_objective_diag": ([vp, vp, i32, vp], C.c_int),
         "dpdlp_cost_params_default": ([C.POINTER(CostParams)], None),
         "dpdlp_cost_step": ([i64, i64, i64, i32, i32, C.POINTER(CostParams), vp], C.c_int),
         "dpdlp_grid_select": ([i64, i64, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
@@ -334,9 +335,12 @@ def dpdlp_problem_destroy(h):
 
 # ---- convenience wrapper ------------------------------------------------------
 class Problem:
-    """A prepared problem on the current GPU (owns the library handle)."""
+    """A prepared problem on the current GPU (owns the library handle).
 
-    def __init__(self, lp, params: Optional[Params] = None, stream=None, **kw):
+    An instance that carries ``lp.q`` (diag(Q), Sec. 6) is set up as a
+    diagonal QP, unless ``q`` is given (an array, or False for the LP)."""
+
+    def __init__(self, lp, params: Optional[Params] = None, stream=None, q=None, **kw):
         prm = params if params is not None else dpdlp_params_default()
         for k, v in kw.items():
             if not hasattr(prm, k):
@@ -346,6 +350,20 @@ class Problem:
         self.m, self.n = int(lp.m), int(lp.n)
         self.stream = stream
         self.h = dpdlp_problem_create(lp, prm, stream)
+        if q is None:
+            q = getattr(lp, "q", None)
+        if q is not None and q is not False:
+            self.set_objective_diag(q)
+
+    def set_objective_diag(self, q):
+        """diag(Q) of a QP objective x^T Q x / 2 (host array), or None for the LP."""
+        if q is None:
+            _check(_lib.dpdlp_set_objective_diag(self.h, None, MEM_HOST, self._s))
+            return
+        qa = np.ascontiguousarray(q, np.float64)
+        if qa.shape != (self.n,):
+            raise ValueError("q must have length n")
+        _check(_lib.dpdlp_set_objective_diag(self.h, _ptr(qa), MEM_HOST, self._s))
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -376,6 +376,37 @@ struct PrimalOp {
     }
 };
 
+// Primal step of a QP with diagonal Q (Sec. 6) over CSC tiles: the step
+// minimises q x^2 / 2 + g x + (x - x_j)^2 / (2 tau) over the box, separately
+// per column, so xh = clamp((x_j - tau g) / (1 + tau q_j), l_j, u_j) (a
+// convex one-dimensional quadratic); the rest is the LP step.  q is the
+// scaled diagonal D_c Q D_c.  A type of its own, so the LP step's kernel
+// arguments and code stay as they are.
+template <typename T>
+struct PrimalQPOp : PrimalOp<T> {
+    using Base = PrimalOp<T>;
+    const T *__restrict__ q;
+    struct Pre { T x, c, lo, hi, xa, q; };
+    __device__ void prefetch(int j, Pre &p) const
+    {
+        p.x = nt_load(this->x + j); p.c = nt_load(this->c + j); p.lo = nt_load(this->lo + j);
+        p.hi = nt_load(this->hi + j); p.xa = nt_load(this->xa + j); p.q = nt_load(q + j);
+    }
+    __device__ void epilogue(int j, const T *r, const Pre &p, double *) const
+    {
+        const T g = p.c - r[0];
+        const T xk = p.x;
+        const T tau = this->tau;
+        const T xhv = clampv((xk - tau * g) / (T(1) + tau * p.q), p.lo, p.hi);
+        this->xbar[j] = T(2) * xhv - xk;
+        nt_store(this->x + j, this->a * ((T(1) + this->gamma) * xhv - this->gamma * xk) + this->b * p.xa);
+        if (this->write_hat) {
+            this->xh[j] = (double)xhv;
+            this->dx[j] = (double)xk - (double)xhv;
+        }
+    }
+};
+
 // Dual step over CSR tiles, one segment per row i:
 //   q = (A~ xbar)_i ; w = y_i / sigma - q ; yh = sigma (w - clamp(w, -u_i, -l_i))
 //   y_i <- a ((1+gamma) yh - gamma y_i) + b ya_i
@@ -612,6 +643,7 @@ struct CheckColOp {
     const double *__restrict__ lo;    // scaled variable bounds
     const double *__restrict__ hi;
     const double *__restrict__ dc;
+    const double *__restrict__ q;     // scaled diagonal of Q, or null (an LP)
     double *partials;
     double tau;
     __device__ void value(MT v, int i, AT *out) const { out[0] = v * yh[i]; }
@@ -619,14 +651,19 @@ struct CheckColOp {
     __device__ void prefetch(int, Pre &) const {}
     __device__ void epilogue(int j, const AT *r, const Pre &, double *acc) const
     {
-        const double g = c[j] - r[0];
+        // a QP (Sec. 6) adds Q x to the gradient, x^T Q x / 2 to the primal
+        // objective and takes it off the dual one; q~ x~ = D_c (Q x) and
+        // q~ x~^2 = x^T Q x per column
+        const double qx = q ? q[j] * xh[j] : 0.0;
+        const double g = c[j] + qx - r[0];
         const double u = xh[j] - tau * g;
         const double s = (clampv(u, lo[j], hi[j]) - u) / tau;
         const double dres = (g - s) / dc[j];
         acc[0] += dres * dres;
         const double xj = dc[j] * xh[j];
-        acc[1] += c0[j] * xj;
-        acc[2] += (s / dc[j]) * xj;
+        const double half_xqx = 0.5 * qx * xh[j];
+        acc[1] += c0[j] * xj + half_xqx;
+        acc[2] += (s / dc[j]) * xj - half_xqx;
         const double dxj = dx[j];
         acc[3] += dxj * dxj;
         const double an = xh[j] - (double)xa[j];

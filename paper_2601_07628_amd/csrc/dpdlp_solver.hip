@@ -388,6 +388,9 @@ struct dpdlp_problem {
     float *x32 = nullptr, *y32 = nullptr, *xbar32 = nullptr, *xa32 = nullptr, *ya32 = nullptr;
     float *c32 = nullptr, *clo32 = nullptr, *chi32 = nullptr, *vlo32 = nullptr, *vhi32 = nullptr;
     double *xbest = nullptr, *ybest = nullptr;  // T(z) of the FP32 phase's best check
+    // diagonal QP (Sec. 6): scaled, permuted diag(Q); used when has_q
+    double *qd = nullptr;
+    bool has_q = false;
     // scratch
     double *tmp_m = nullptr, *tmp_n = nullptr, *tmp_m2 = nullptr, *tmp_n2 = nullptr;
     double *scal = nullptr;         // device scalars: [4..7] norms, [8] beta, [9] alpha (Lanczos)
@@ -515,6 +518,24 @@ static void prof_collect(dpdlp_problem *P)
 }
 
 // ---- the fused steps -------------------------------------------------------
+// The primal step with its epilogue Op (PrimalOp, or PrimalQPOp for a QP):
+// sliced (per-slice partial sums, then the combine runs the epilogue) or on
+// the CSC tiles.
+template <typename T, class Op>
+static void run_primal(dpdlp_problem *P, const Op &op, const T *y, const T *vt)
+{
+    if (P->sc.S > 0) {
+        PartialOp<T> po;
+        po.v = y; po.partial = (T *)P->part_slices; po.partials = nullptr;
+        launch_tiles(P, po, P->sc.ts, P->sc.ptr, P->sc.idx,
+                     (const T *)(sizeof(T) == 8 ? (const void *)P->sc.val : (const void *)P->sc.val32));
+        hipLaunchKernelGGL(k_combine<Op>, dim3(nblk(P->n)), dim3(kBlock), 0, P->s, op, P->n,
+                           P->sc.S, (const T *)P->part_slices, P->sc.mask, P->sc.cbase, P->sc.G);
+        return;
+    }
+    launch_tiles(P, op, P->tc, P->cp, P->ri, vt);
+}
+
 template <typename T>
 static void launch_primal(dpdlp_problem *P, const T *y, const T *c, const T *lo, const T *hi,
                           const T *xa, T *x, T *xbar, const T *vt, double tau, int64_t k,
@@ -530,16 +551,16 @@ static void launch_primal(dpdlp_problem *P, const T *y, const T *c, const T *lo,
     op.b = (T)(1.0 / (double)(k + 2));
     op.gamma = (T)P->prm.gamma;
     op.write_hat = write_hat;
-    if (P->sc.S > 0) {
-        PartialOp<T> po;
-        po.v = y; po.partial = (T *)P->part_slices; po.partials = nullptr;
-        launch_tiles(P, po, P->sc.ts, P->sc.ptr, P->sc.idx,
-                     (const T *)(sizeof(T) == 8 ? (const void *)P->sc.val : (const void *)P->sc.val32));
-        hipLaunchKernelGGL(k_combine<PrimalOp<T>>, dim3(nblk(P->n)), dim3(kBlock), 0, P->s, op, P->n,
-                           P->sc.S, (const T *)P->part_slices, P->sc.mask, P->sc.cbase, P->sc.G);
-        return;
+    if constexpr (sizeof(T) == 8) {
+        if (P->has_q) {             // FP64 only (a QP cannot be created in FP32-mixed mode)
+            PrimalQPOp<T> qop;
+            static_cast<PrimalOp<T> &>(qop) = op;
+            qop.q = P->qd;
+            run_primal<T>(P, qop, y, vt);
+            return;
+        }
     }
-    launch_tiles(P, op, P->tc, P->cp, P->ri, vt);
+    run_primal<T>(P, op, y, vt);
 }
 
 template <typename T>
@@ -685,6 +706,7 @@ static void launch_checks(dpdlp_problem *P, const double *xh, const double *dx, 
         CheckColOp<TA> op;
         op.yh = yh; op.xh = xh; op.dx = dx; op.xa = xa; op.c = P->c; op.c0 = P->c0;
         op.lo = P->vlo; op.hi = P->vhi; op.dc = P->dc; op.partials = P->part_c; op.tau = tau;
+        op.q = P->has_q ? P->qd : nullptr;
         if (P->sc.S > 0) {
             PartialOp<double> po;
             po.v = yh; po.partial = (double *)P->part_slices; po.partials = nullptr;
@@ -1506,6 +1528,46 @@ int dpdlp_set_params(dpdlp_problem *P, const dpdlp_params *q)
     return DPDLP_OK;
 }
 
+int dpdlp_set_objective_diag(dpdlp_problem *P, const double *q, int32_t mem_kind, void *stream)
+{
+    ENTER(P);
+    const int32_t n = P->n;
+    if (!q) {
+        P->has_q = false;
+        drop_graphs(P);             // the primal step's kernel is a captured node
+        return DPDLP_OK;
+    }
+    if (P->prm.precision != DPDLP_FP64) {
+        set_error("a diagonal quadratic objective needs precision DPDLP_FP64");
+        return DPDLP_E_NOT_SUPPORTED;
+    }
+    if (mem_kind != DPDLP_MEM_HOST && mem_kind != DPDLP_MEM_DEVICE) {
+        set_error("bad mem_kind");
+        return DPDLP_E_INVALID_ARG;
+    }
+    std::vector<double> h((size_t)n), dc((size_t)n), out((size_t)n);
+    if (mem_kind == DPDLP_MEM_DEVICE)
+        HIPCHK(hipMemcpy(h.data(), q, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+    else
+        std::memcpy(h.data(), q, sizeof(double) * (size_t)n);
+    for (int32_t j = 0; j < n; ++j)
+        if (!std::isfinite(h[(size_t)j]) || h[(size_t)j] < 0.0) {
+            set_error("diag(Q) must be finite and >= 0 (index " + std::to_string(j) + ")");
+            return DPDLP_E_INVALID_ARG;
+        }
+    HIPCHK(hipStreamSynchronize(P->s));
+    HIPCHK(hipMemcpy(dc.data(), P->dc, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+    // permuted column j holds original column h_perm_col[j]; the scaled
+    // problem's Q is D_c Q D_c
+    for (int32_t j = 0; j < n; ++j)
+        out[(size_t)j] = dc[(size_t)j] * dc[(size_t)j] * h[(size_t)P->h_perm_col[(size_t)j]];
+    if (!P->qd) CHK(dalloc(P, &P->qd, (size_t)n));
+    HIPCHK(hipMemcpy(P->qd, out.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice));
+    P->has_q = true;
+    drop_graphs(P);
+    return DPDLP_OK;
+}
+
 int dpdlp_init(dpdlp_problem *P, const double *x0, const double *y0, int32_t mem_kind, void *stream)
 {
     ENTER(P);
@@ -1784,7 +1846,8 @@ int dpdlp_get_profile(dpdlp_problem *P, double *total_ms, int64_t *launches, dou
     const bool f32 = P->in_fp32;
     const double vb = f32 ? 4.0 : 8.0, mb = f32 ? 4.0 : 8.0;
     const double bpl[8] = {
-        z * (4.0 + mb) + 4.0 * (n + 1) + 7 * vb * n + vb * m,     // primal: CSC, x c l u xa, xbar x, y
+        z * (4.0 + mb) + 4.0 * (n + 1) + (P->has_q ? 8 : 7) * vb * n + vb * m,  // primal: CSC,
+                                                                  // x c l u xa (q), xbar x, y
         z * (4.0 + mb) + 4.0 * (m + 1) + 5 * vb * m + vb * n,     // dual: CSR, y l u ya, y, xbar
         z * 24.0 / 2 + 4.0 * (m + 1) + 16.0 * n + 8.0 * 7 * m,    // check CSR
         z * 24.0 / 2 + 4.0 * (n + 1) + 8.0 * m + 8.0 * 7 * n,     // check CSC
