@@ -38,9 +38,11 @@ def test_qp_kkt_matches_oracle(D, O):
     G = D.Problem(lp, gpu_params(D))
     P = O.Problem(lp)
     rng = np.random.default_rng(1)
+    ge = np.isinf(lp.con_hi)              # '>=' rows: y >= 0 keeps the dual objective finite
     for _ in range(3):
         x = rng.uniform(0, 10, lp.n)
         y = rng.standard_normal(lp.m)
+        y[ge] = np.abs(y[ge])
         for tau in (0.01, 1.0):
             g = G.kkt(x, y, tau=tau)
             o = P.kkt(x, y, tau=tau)
