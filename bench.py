@@ -365,8 +365,26 @@ def main():
                               "csr_ms": round(ms_r, 4), "csc_ms": round(ms_c, 4)}
         log(f"SpMV: {extra['spmv_GBps']}")
 
+    def stream_copy():
+        # measured HBM ceiling next to the 8 TB/s peak: a 2 GiB device-to-
+        # device copy (bytes read + written per second), best of 5
+        src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        best = float("inf")
+        for _ in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            dst.copy_(src)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        extra["stream_copy_GBps"] = round(2 * src.numel() * 8 / (best * 1e-3) / 1e9, 1)
+        log(f"stream copy: {extra['stream_copy_GBps']} GB/s")
+        del src, dst
+
     if not args.no_extra:
         guarded("spmv", spmv)
+        guarded("stream_copy", stream_copy)
     G.close()
     del G
 

@@ -212,9 +212,9 @@ int dpdlp_set_params(dpdlp_problem *prob, const dpdlp_params *params);
  * residual, x^T Q x / 2 to the primal objective and takes it off the dual
  * objective.  Scaling, step size and primal weight stay those of the LP
  * part.  Call before dpdlp_init / dpdlp_solve (a later call takes effect
- * from the next iteration).  FP64 only: NOT_SUPPORTED when the problem was
- * created with DPDLP_FP32_MIXED.  INVALID_ARG for a negative or non-finite
- * entry or a bad mem_kind.                                                */
+ * from the next iteration).  In DPDLP_FP32_MIXED mode the FP32 phase uses
+ * an FP32 copy of the scaled diag(Q); the checks use the FP64 one.
+ * INVALID_ARG for a negative or non-finite entry or a bad mem_kind.       */
 int dpdlp_set_objective_diag(dpdlp_problem *prob, const double *q, int32_t mem_kind,
                              void *stream);
 

@@ -388,8 +388,10 @@ struct dpdlp_problem {
     float *x32 = nullptr, *y32 = nullptr, *xbar32 = nullptr, *xa32 = nullptr, *ya32 = nullptr;
     float *c32 = nullptr, *clo32 = nullptr, *chi32 = nullptr, *vlo32 = nullptr, *vhi32 = nullptr;
     double *xbest = nullptr, *ybest = nullptr;  // T(z) of the FP32 phase's best check
-    // diagonal QP (Sec. 6): scaled, permuted diag(Q); used when has_q
+    // diagonal QP (Sec. 6): scaled, permuted diag(Q) (and its FP32 copy in
+    // FP32-mixed mode); used when has_q
     double *qd = nullptr;
+    float *q32 = nullptr;
     bool has_q = false;
     // scratch
     double *tmp_m = nullptr, *tmp_n = nullptr, *tmp_m2 = nullptr, *tmp_n2 = nullptr;
@@ -551,14 +553,13 @@ static void launch_primal(dpdlp_problem *P, const T *y, const T *c, const T *lo,
     op.b = (T)(1.0 / (double)(k + 2));
     op.gamma = (T)P->prm.gamma;
     op.write_hat = write_hat;
-    if constexpr (sizeof(T) == 8) {
-        if (P->has_q) {             // FP64 only (a QP cannot be created in FP32-mixed mode)
-            PrimalQPOp<T> qop;
-            static_cast<PrimalOp<T> &>(qop) = op;
-            qop.q = P->qd;
-            run_primal<T>(P, qop, y, vt);
-            return;
-        }
+    if (P->has_q) {
+        PrimalQPOp<T> qop;
+        static_cast<PrimalOp<T> &>(qop) = op;
+        if constexpr (sizeof(T) == 8) qop.q = P->qd;
+        else qop.q = P->q32;
+        run_primal<T>(P, qop, y, vt);
+        return;
     }
     run_primal<T>(P, op, y, vt);
 }
@@ -1537,10 +1538,6 @@ int dpdlp_set_objective_diag(dpdlp_problem *P, const double *q, int32_t mem_kind
         drop_graphs(P);             // the primal step's kernel is a captured node
         return DPDLP_OK;
     }
-    if (P->prm.precision != DPDLP_FP64) {
-        set_error("a diagonal quadratic objective needs precision DPDLP_FP64");
-        return DPDLP_E_NOT_SUPPORTED;
-    }
     if (mem_kind != DPDLP_MEM_HOST && mem_kind != DPDLP_MEM_DEVICE) {
         set_error("bad mem_kind");
         return DPDLP_E_INVALID_ARG;
@@ -1563,6 +1560,14 @@ int dpdlp_set_objective_diag(dpdlp_problem *P, const double *q, int32_t mem_kind
         out[(size_t)j] = dc[(size_t)j] * dc[(size_t)j] * h[(size_t)P->h_perm_col[(size_t)j]];
     if (!P->qd) CHK(dalloc(P, &P->qd, (size_t)n));
     HIPCHK(hipMemcpy(P->qd, out.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice));
+    if (P->prm.precision == DPDLP_FP32_MIXED) {
+        // the FP32 phase's copy (its checks use the FP64 one)
+        if (!P->q32) CHK(dalloc(P, &P->q32, (size_t)n));
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(n)), dim3(kBlock), 0, P->s, P->qd,
+                           P->q32, (int64_t)n);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(P->s));
+    }
     P->has_q = true;
     drop_graphs(P);
     return DPDLP_OK;

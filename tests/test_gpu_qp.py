@@ -106,5 +106,38 @@ def test_qp_argument_errors(D):
     bad[3] = np.nan
     with pytest.raises(RuntimeError, match="diag"):
         G.set_objective_diag(bad)
-    with pytest.raises(RuntimeError, match="FP64"):
-        D.Problem(lp, gpu_params(D, precision=D.FP32_MIXED))
+    with pytest.raises(ValueError):
+        G.set_objective_diag(lp.q[:-1])
+
+
+@pytest.mark.parametrize("name,maker", [
+    ("constructed-qp", lambda: lpgen.constructed_qp(2000, 4000, 1000, 5, seed=26)),
+    ("lasso", lambda: lpgen.lasso_qp(3000, 1500, 12, seed=6))])
+def test_qp_fp32_mixed_iterates_against_fp64_oracle(D, O, name, maker):
+    """FP32-mixed QP iterates against the FP64 oracle after one 64-iteration
+    epoch from the same start and step sizes, to the FP32 bar of the LP
+    tests (1e-5 relative)."""
+    lp = maker()
+    P0 = O.Problem(lp)
+    eta, w0 = P0.eta, P0.omega0
+    P = O.Problem(lp, O.Params(eta=eta, omega0=w0, eps=0.0))
+    st = P.init_state()
+    P.run(st, 64)
+    G = D.Problem(lp, gpu_params(D, eta=eta, omega0=w0, eps=0.0, precision=D.FP32_MIXED,
+                                 fp32_switch_tol=0.0, fp32_stall_checks=10**6, fp32_diverge=0.0))
+    G.init()
+    G.iterate(64)
+    gs = G.state()
+    assert [e["restart"] for e in G.log()] == [e["restart"] for e in st["log"]]
+    errs = {k: rel(gs[k], st[k]) for k in ("xh", "yh")}
+    print(f"{name}: FP32-mixed QP vs FP64 oracle after 64 iterations: {errs}")
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_qp_fp32_mixed_solves_to_1e8(D, O):
+    lp = lpgen.constructed_qp(2000, 4000, 1000, 5, seed=27)
+    r = D.Problem(lp, gpu_params(D, eps=1e-8, precision=D.FP32_MIXED)).solve()
+    assert r["status"] == D.CONVERGED
+    assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= 1e-8
+    assert r["fp32_iters"] > 0
+    assert abs(r["obj_primal"] - lp.obj_star) <= 1e-6 * (1 + abs(lp.obj_star))
