@@ -537,6 +537,29 @@ def main():
         if not args.no_warmstart:
             guarded("warm_start_c4", ws)
 
+    def cost_model():
+        # the paper's per-iteration model (App. E) with MI355X constants, for
+        # this instance on 1..8 GPUs, next to the measured one-GPU time; once
+        # with the 8 TB/s peak and once with the measured copy ceiling
+        out = {"measured_ms_per_iter_1gpu": round(1e3 / value, 4)}
+        bms = [("peak", None)]
+        if extra.get("stream_copy_GBps"):
+            bms.append(("measured_copy", extra["stream_copy_GBps"] * 1e9))
+        for tag, bm in bms:
+            cp = D.dpdlp_cost_params_default(**({} if bm is None else {"b_mem": bm}))
+            row = {}
+            for N in (1, 2, 4, 8):
+                R, Cc = D.dpdlp_grid_select(lp.m, lp.n, N)
+                row[str(N)] = {"grid": f"{R}x{Cc}", "ms": round(
+                    1e3 * D.dpdlp_cost_step(lp.m, lp.n, lp.nnz, R, Cc, cp)["total"], 4)}
+            out[f"b_mem_{tag}"] = {"b_mem_GBps": round(cp.b_mem / 1e9, 1), "predicted": row,
+                                   "auto": D.dpdlp_auto_devices(lp.m, lp.n, lp.nnz, params=cp)}
+        extra["cost_model_c1"] = out
+        log(f"cost model: {out}")
+
+    if not args.no_extra:
+        guarded("cost_model_c1", cost_model)
+
     cpu = None
     if not args.no_cpu:
         log(f"CPU baseline: oracle, {args.cpu_iters} iterations on config 1")
