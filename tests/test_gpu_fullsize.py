@@ -3,7 +3,8 @@ configuration bench.py times (default parameters: 2048-nonzero tiles, XCD
 remap on, block permutation B = 256, automatic XCD slicing, which slices
 c1's dual step), plus slicing off and slicing of both steps.
 
-c1 (m 2M, n 4M, 40M nonzeros) and c2 (m 6000, n 9M, 18M nonzeros): both
+c1 (m 2M, n 4M, 40M nonzeros), c2 (m 6000, n 9M, 18M nonzeros) and the
+LASSO QP of the benchmark (m 2M, n 2M, 22.9M nonzeros): both
 sides run the first iterations from the same start with the same eta and
 omega0 (the step size comes from a short power estimate of the oracle, so no
 oracle input comes from the GPU); the oracle computes every output, and all
@@ -68,3 +69,10 @@ def test_c1_fullsize_two_check_blocks_with_graph_replay(D):
 
 def test_c2_fullsize_parity(D):
     _fullsize(D, lpgen.config2(), 3)
+
+
+def test_lasso_qp_fullsize_parity(D):
+    """The diagonal QP at the size bench.py times (the LASSO of App. J on
+    1M samples x 500k features, 22.9M nonzeros; default parameters),
+    70 iterations: one full check block plus the next check."""
+    _fullsize(D, lpgen.lasso_qp(1_000_000, 500_000, 20, seed=7), 70, -1)
