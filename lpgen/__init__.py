@@ -64,6 +64,7 @@ class LP:
     y_star: Optional[np.ndarray] = None   # constructed dual optimum, if any
     obj_star: Optional[float] = None      # objective at the constructed optimum
     q: Optional[np.ndarray] = None        # diagonal of Q for a QP (x^T Q x / 2), else None
+    lasso: Optional[dict] = None          # LASSO data (A, b, lam) of a lasso_qp instance
 
     @property
     def nnz(self) -> int:
@@ -233,10 +234,9 @@ def lasso_qp(samples: int, features: int, per_row: int, seed: int,
     q = np.concatenate([np.zeros(n_x), np.ones(n_r), np.zeros(features)])
     var_lo = np.concatenate([np.full(n_x + n_r, -INF), np.zeros(features)])
     var_hi = np.full(n_cols, INF)
-    lp = LP(m_rows, n_cols, M.indptr.astype(np.int32), M.indices.astype(np.int32),
-            M.data.astype(np.float64), c, con_lo, con_hi, var_lo, var_hi, name=name, q=q)
-    lp.lasso = dict(A=A, b=b, lam=lam)
-    return lp
+    return LP(m_rows, n_cols, M.indptr.astype(np.int32), M.indices.astype(np.int32),
+              M.data.astype(np.float64), c, con_lo, con_hi, var_lo, var_hi, name=name, q=q,
+              lasso=dict(A=A, b=b, lam=lam))
 
 
 def config0() -> LP:
