@@ -272,6 +272,9 @@ def test_split_segments_long_row_and_column(D, O):
     fixed_run(D, O, lp, 300)
     fixed_run(D, O, lp, 300, gpu_kw=dict(tile_nnz=512))
     fixed_run(D, O, lp, 300, gpu_kw=dict(tile_nnz=512, gather_slices=8))
+    # 16 slices of equal nonzero counts: the long row holds more than one
+    # slice's share, so the slice after it is empty
+    fixed_run(D, O, lp, 300, gpu_kw=dict(tile_nnz=512, gather_slices=16))
 
 
 @pytest.mark.parametrize("slices", [-1, 8, 16])
