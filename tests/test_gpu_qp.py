@@ -141,3 +141,46 @@ def test_qp_fp32_mixed_solves_to_1e8(D, O):
     assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= 1e-8
     assert r["fp32_iters"] > 0
     assert abs(r["obj_primal"] - lp.obj_star) <= 1e-6 * (1 + abs(lp.obj_star))
+
+
+def test_qp_diag_from_device_memory(D):
+    """diag(Q) handed over as device memory gives the same iterates as the
+    host copy."""
+    import torch
+    lp = lpgen.constructed_qp(500, 1000, 250, 4, seed=28)
+    G1 = D.Problem(lp, gpu_params(D))
+    G1.init()
+    G1.iterate(150)
+    G2 = D.Problem(lp, gpu_params(D), q=False)
+    qd = torch.tensor(lp.q, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    rc = D.lib().dpdlp_set_objective_diag(G2.h, qd.data_ptr(), D.MEM_DEVICE, None)
+    assert rc == 0, D.dpdlp_last_error()
+    G2.init()
+    G2.iterate(150)
+    s1, s2 = G1.state(), G2.state()
+    for k in ("x", "y", "xh", "yh"):
+        assert np.array_equal(s1[k], s2[k])
+
+
+def test_qp_set_mid_run_matches_oracle(D, O):
+    """diag(Q) set after 100 LP iterations takes effect from the next
+    iteration (the replayed graph of the LP step is dropped): 100 more
+    iterations match the oracle, which switches at the same point."""
+    lp = lpgen.constructed_qp(1000, 2000, 500, 4, seed=29)
+    plain = dataclasses.replace(lp, q=None)
+    P0 = O.Problem(plain)
+    eta, w0 = P0.eta, P0.omega0
+    P = O.Problem(plain, O.Params(eta=eta, omega0=w0, eps=0.0))
+    st = P.init_state()
+    P.run(st, 100)
+    O.lib().ora_set_qdiag(P._h, lp.q.ctypes.data)
+    P.run(st, 100)
+    G = D.Problem(plain, gpu_params(D, eta=eta, omega0=w0, eps=0.0))
+    G.init()
+    G.iterate(100)
+    G.set_objective_diag(lp.q)
+    G.iterate(100)
+    gs = G.state()
+    for k in ("x", "y", "xh", "yh"):
+        assert rel(gs[k], st[k]) <= 1e-10, (k, rel(gs[k], st[k]))
