@@ -275,6 +275,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 256 MiB buffer (device to device), a kernel of "
                          "known size that calibrates the HBM byte counters")
+    ap.add_argument("--workload", choices=("c1", "c2", "lasso"), default="c1",
+                    help="the instance of the timed steps: c1 (the benchmark), or, for "
+                         "profiling the other paths, c2 (transportation LP) or lasso "
+                         "(the diagonal-QP LASSO); the latter two imply --no-extra --no-cpu")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark, run the permutation x partition "
                          "ablation on config 1 and its staircase variant")
@@ -307,10 +311,13 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 268435456 bytes read, 268435456 bytes written")
         del src, dst
-    log("generating config 1 (m=2M, n=4M, ~40M nonzeros)")
+    if args.workload != "c1":
+        args.no_extra = args.no_cpu = True
+    log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
-    lp = lpgen.config1()
-    log(f"config 1 ready in {time.perf_counter() - t0:.1f} s: {lp.describe()}")
+    lp = {"c1": lpgen.config1, "c2": lpgen.config2,
+          "lasso": lambda: lpgen.lasso_qp(1_000_000, 500_000, 20, seed=7)}[args.workload]()
+    log(f"{args.workload} ready in {time.perf_counter() - t0:.1f} s: {lp.describe()}")
 
     G = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9), stream=stream)
     s = G.scaling()
@@ -335,7 +342,7 @@ def main():
     dom = max(fused, key=lambda k: fused[k]["total_ms"])
     avg_ms = fused[dom]["total_ms"] / fused[dom]["launches"]
     achieved = fused[dom]["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(dom, "c1")
+    traffic = load_traffic(dom, args.workload)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "kernel": f"fused_{dom}_step_fp64",
@@ -579,8 +586,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded generator; the paper's data sets are not available)",
-        "config": {"workload": "c1: one GPU's share of a huge LP, m=2,000,000, n=4,000,000, "
-                               f"nnz={lp.nnz}, Zipf column degrees, 10% heavy rows, FP64",
+        "config": {"workload": {
+                       "c1": "c1: one GPU's share of a huge LP, m=2,000,000, n=4,000,000, "
+                             f"nnz={lp.nnz}, Zipf column degrees, 10% heavy rows, FP64",
+                       "c2": f"c2: 3000 x 3000 transportation LP, m=6,000, n=9,000,000, "
+                             f"nnz={lp.nnz}, FP64",
+                       "lasso": f"LASSO as diagonal QP, 1M samples x 500k features, m={lp.m}, "
+                                f"n={lp.n}, nnz={lp.nnz}, FP64"}[args.workload],
                    "iters_per_step": ips, "check_period": 64, "m": lp.m, "n": lp.n,
                    "nnz": lp.nnz},
         "roofline": roof,
