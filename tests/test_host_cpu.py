@@ -181,3 +181,14 @@ def test_row_bounds_from_row_types(D):
         D.dpdlp_row_bounds(b, [0, 1, 3, 1])
     with pytest.raises(D.DpdlpError, match="finite"):
         D.dpdlp_row_bounds([np.inf], [1])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message before touching a GPU
+    (the library has no multi-GPU path)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
