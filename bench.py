@@ -100,17 +100,22 @@ def cpu_baseline(lp, n_iters):
                 seconds=el)
 
 
-def time_to_tol(D, lp, torch, **kw):
+def time_to_tol(D, lp, torch, reps=5, **kw):
+    """Solve time to 1e-4 and 1e-8: one warm-up solve, then the median of
+    `reps` timed solves of the same handle (setup excluded, reported)."""
     out = {}
     for eps in (1e-4, 1e-8):
         G = D.Problem(lp, gpu_params(D, eps=eps, **kw), stream=torch.cuda.current_stream())
         G.solve()                              # warm-up (kernels, allocator)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = G.solve()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out[f"{eps:g}"] = dict(seconds=round(el, 5), iters=int(r["iters"]),
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = G.solve()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        el = sorted(times)[len(times) // 2]
+        out[f"{eps:g}"] = dict(seconds=round(el, 5), runs=reps, iters=int(r["iters"]),
                                status=D.dpdlp_status_string(r["status"]),
                                kkt=max(r["r_primal"], r["r_dual"], r["r_gap"]),
                                obj=r["obj_primal"], fp32_iters=int(r["fp32_iters"]),
