@@ -474,3 +474,225 @@ def test_constructed_qp_solves_to_its_optimum(oracle_mod):
     r = oracle_mod.Problem(lp).solve(max_iters=300_000)
     assert r["status"] == 1
     assert abs(r["obj_p"] - lp.obj_star) <= 1e-7 * (1 + abs(lp.obj_star))
+
+
+# -- A7 off the optimum: App. B.4's formulas evaluated directly -----------------
+def _mixed_bounds_lp(seed, m=60, n=90):
+    """A sparse LP with every row type of Sec. 2.1 ('=', '>=', '<=', ranged,
+    free) and every variable-bound type (box, upper only, lower only, free),
+    with entries spread over four orders of magnitude so that scaling moves
+    every D_r and D_c entry away from one."""
+    rng = np.random.default_rng(seed)
+    A = sp.random(m, n, density=0.08, random_state=rng, format="csr",
+                  data_rvs=lambda k: rng.standard_normal(k) * 10.0 ** rng.uniform(-2, 2, k))
+    A = A.toarray()
+    A[np.arange(m), np.arange(m) % n] += 1.0          # no empty row
+    kind = np.arange(m) % 5
+    b = rng.standard_normal(m)
+    lo = np.select([kind == 0, kind == 1, kind == 2, kind == 3, kind == 4],
+                   [b, b, -np.inf, b - 1.0, -np.inf])
+    hi = np.select([kind == 0, kind == 1, kind == 2, kind == 3, kind == 4],
+                   [b, np.inf, b, b + 2.0, np.inf])
+    vk = np.arange(n) % 4
+    vlo = np.select([vk == 0, vk == 1, vk == 2, vk == 3], [-1.0, -np.inf, -3.0, -np.inf])
+    vhi = np.select([vk == 0, vk == 1, vk == 2, vk == 3], [2.0, 5.0, np.inf, np.inf])
+    return lpgen.from_dense(A, rng.standard_normal(n), lo, hi, vlo, vhi, name="mixed")
+
+
+def _point_in_x_and_y(lp, seed):
+    rng = np.random.default_rng(seed)
+    x = np.clip(3.0 * rng.standard_normal(lp.n), lp.var_lo, lp.var_hi)
+    y = 2.0 * rng.standard_normal(lp.m)
+    lo_f, hi_f = np.isfinite(lp.con_lo), np.isfinite(lp.con_hi)
+    y = np.where(lo_f & hi_f, y, np.where(lo_f, np.abs(y), np.where(hi_f, -np.abs(y), 0.0)))
+    return x, y
+
+
+def _kkt_app_b4(lp, x, y, tau):
+    """r_primal, r_dual, r_gap and both objectives, written from App. B.4 and
+    Sec. 2.1 as printed: proj_S and proj_X are clips, p(y; l, u) =
+    u^T y+ - l^T y- (an infinite bound meets a zero part), and s is the
+    projection's displacement divided by tau.  tau may be a vector (a
+    per-column step)."""
+    A = lp.scipy_csr().toarray()
+    ax = A @ x
+    finite = np.concatenate([lp.con_lo[np.isfinite(lp.con_lo)],
+                             lp.con_hi[np.isfinite(lp.con_hi)]])
+    r_primal = np.linalg.norm(ax - np.clip(ax, lp.con_lo, lp.con_hi)) / (1 + np.linalg.norm(finite))
+    u = x - tau * (lp.c - A.T @ y)
+    pu = np.clip(u, lp.var_lo, lp.var_hi)
+    r_dual = np.linalg.norm((pu - x) / tau) / (1 + np.linalg.norm(lp.c))
+    s = (pu - u) / tau
+    yp, ym = np.maximum(-y, 0.0), np.maximum(y, 0.0)          # (-y)+ and (-y)-
+    p_neg_y = (np.sum(lp.con_hi[yp > 0] * yp[yp > 0])
+               - np.sum(lp.con_lo[ym > 0] * ym[ym > 0]))      # p(-y; l_c, u_c)
+    cx = lp.c @ x
+    dual_obj = -p_neg_y + s @ x
+    r_gap = abs(cx + p_neg_y - s @ x) / (1 + max(abs(cx), abs(dual_obj)))
+    return np.array([r_primal, r_dual, r_gap, cx, dual_obj])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("tau", [1e-3, 0.3, 5.0])
+def test_kkt_off_optimum_matches_app_b4_unscaled(oracle_mod, seed, tau):
+    """With scaling off (D_r = D_c = I) the oracle's KKT at a random
+    non-optimal point of X x Y equals App. B.4 evaluated directly, for every
+    row and bound type: the residual norms, the gap, and both objectives.
+    The oracle forms the dual residual as (c - A^T y) - s; here it is the
+    printed ||proj_X(x - tau(c - A^T y)) - x|| / tau, another route."""
+    lp = _mixed_bounds_lp(seed)
+    x, y = _point_in_x_and_y(lp, seed + 10)
+    P = oracle_mod.Problem(lp, _prm(oracle_mod, ruiz_iters=0, use_pc=0, eta=1.0, omega0=1.0))
+    d = P.scaled()
+    assert np.all(d["dr"] == 1.0) and np.all(d["dc"] == 1.0)
+    got = P.kkt(x, y, tau=tau)
+    ref = _kkt_app_b4(lp, x, y, tau)
+    assert np.all(ref[:3] > 1e-3), ref                    # far from optimal
+    assert np.allclose(got, ref, rtol=1e-13, atol=0), (got, ref)
+
+
+@pytest.mark.parametrize("tau", [1e-3, 0.3, 5.0])
+def test_kkt_through_scaling_is_app_b4_in_original_space(oracle_mod, tau):
+    """The scaled-path KKT (the reading that evaluates at the scaled T(z) and
+    maps back: A x = D_r^-1 A~ x~, s = D_c^-1 s~) against the original-space
+    formulas.  The primal residual is the printed one.  The primal step of
+    the scaled problem with step tau, mapped back, is the original problem's
+    step with the per-column step tau D_c^2, so r_dual and r_gap are App. B.4
+    with that vector of steps.  A dropped or inverted D_c anywhere in the
+    mapping, or D_r in place of D_c, fails here."""
+    lp = _mixed_bounds_lp(3)
+    x, y = _point_in_x_and_y(lp, 13)
+    P = oracle_mod.Problem(lp, _prm(oracle_mod, eta=1.0, omega0=1.0))
+    dc = P.scaled()["dc"]
+    assert dc.max() / dc.min() > 10.0                    # scaling is far from I
+    got = P.kkt(x, y, tau=tau)
+    ref = _kkt_app_b4(lp, x, y, tau * dc ** 2)
+    assert np.isclose(got[0], _kkt_app_b4(lp, x, y, tau)[0], rtol=1e-12, atol=0)
+    assert np.allclose(got, ref, rtol=1e-12, atol=0), (got, ref)
+    # a uniform step would not do once the clamps bind (at tau = 1e-3 hardly
+    # any does, and then r_dual is ||c - A^T y|| under either step)
+    if tau >= 0.3:
+        assert not np.isclose(got[1], _kkt_app_b4(lp, x, y, tau)[1], rtol=1e-3)
+
+
+# -- A8: the fixed-point residual is the P-norm of z - T(z) ------------------------
+def test_restart_residual_is_the_p_norm_of_the_step(oracle_mod):
+    """r at a check equals sqrt(dz^T P dz) with dz = z - T(z) and the
+    block matrix P = [[omega/eta I, A~^T], [A~, 1/(eta omega) I]] of App. B
+    assembled explicitly (scaled space), at the first check (k = 0) and at
+    the check of iteration 63."""
+    lp = lpgen.constructed_lp(40, 70, 20, 3, seed=21)
+    P = oracle_mod.Problem(lp)
+    d = P.scaled()
+    At = sp.csr_matrix((d["v"], lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n)).toarray()
+    for t_check in (0, 63):
+        st = P.init_state()
+        if t_check:
+            P.run(st, t_check)                         # iterations 0 .. t_check-1
+        x, y = st["x"].copy(), st["y"].copy()
+        xa, ya = st["xa"].copy(), st["ya"].copy()
+        S = st["state"]
+        w = S.omega
+        o = P.step(x, y, xa, ya, S.k, P.eta / w, P.eta * w)
+        P.run(st, 1)                                   # the check itself
+        e = st["log"][-1]
+        assert e["t"] == t_check
+        dz = np.concatenate([x - o["xh"], y - o["yh"]])
+        Pm = np.block([[w / P.eta * np.eye(lp.n), At.T], [At, np.eye(lp.m) / (P.eta * w)]])
+        assert np.isclose(e["r"], np.sqrt(dz @ Pm @ dz), rtol=1e-11), (e["r"], np.sqrt(dz @ Pm @ dz))
+
+
+# -- A8: the restart rule, in both directions -------------------------------------
+def _replay_restart_rule(log, beta_suf, beta_nec, beta_art):
+    """Decisions of App. B.2 recomputed from each check's (t, k, r) alone:
+    r0 is r at the epoch's k = 0 check, the 'previous' residual is the
+    previous check of the same epoch, and the three tests run in the order
+    sufficient, necessary, artificial."""
+    out, r0, r_prev = [], None, None
+    for e in log:
+        if e["k"] == 0:
+            r0, r_prev = e["r"], e["r"]
+            out.append(0)
+            continue
+        r = e["r"]
+        if r <= beta_suf * r0:
+            kind = 1
+        elif r <= beta_nec * r0 and r > r_prev:
+            kind = 2
+        elif e["k"] >= beta_art * e["t"]:
+            kind = 3
+        else:
+            kind = 0
+        out.append(kind)
+        r_prev = r
+    return out
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(beta_suf=0.5), dict(beta_nec=0.95),
+                                dict(beta_art=0.1), dict(beta_suf=0.0, beta_nec=0.0)])
+def test_restart_rule_both_directions(oracle_mod, kw):
+    """Every check's decision, restart or not, equals the rule replayed from
+    the logged residuals, so a rule that never fires one kind, or fires when
+    it should not, fails.  The default constants fire all three kinds on
+    config 0; the other constants move the thresholds."""
+    prm = _prm(oracle_mod, max_iters=20000, **kw)
+    lp = lpgen.config0()
+    r = oracle_mod.Problem(lp, prm).solve()
+    log = r["state"]["log"]
+    want = _replay_restart_rule(log, prm.beta_suf, prm.beta_nec, prm.beta_art)
+    if r["status"] == 1:
+        want[-1] = 0                                   # the converged check
+    assert [e["restart"] for e in log] == want
+    if not kw:
+        assert {1, 2, 3} <= set(want)
+    # after a restart the next iteration opens an epoch with a check
+    for a, b in zip(log, log[1:]):
+        if a["restart"]:
+            assert b["k"] == 0 and b["t"] == a["t"] + 1
+
+
+def test_restart_rule_forced_firing(oracle_mod):
+    """Constants that force each kind: beta_art = 0 restarts at every check
+    after an epoch's first (artificial unless a decay test fired first);
+    beta_suf = 1e9 makes every such check a sufficient-decay restart."""
+    lp = lpgen.config0()
+    for kw, kind in ((dict(beta_suf=0.0, beta_nec=0.0, beta_art=0.0), 3),
+                     (dict(beta_suf=1e9), 1)):
+        r = oracle_mod.Problem(lp, _prm(oracle_mod, max_iters=2000, eps=0.0, **kw)).solve()
+        log = r["state"]["log"]
+        assert len(log) > 10
+        for e in log:
+            assert e["restart"] == (0 if e["k"] == 0 else kind), (kw, e)
+
+
+# -- start point: scaled, clamped into X, projected onto Y (Sec. 2.1) -------------
+def test_init_state_projects_the_given_start(oracle_mod):
+    """A given (x0, y0) is mapped to the scaled space and projected: x onto
+    the box, y onto Y_i of Sec. 2.1 per row type ({0} free, R- '<=' only,
+    R+ '>=' only, R with both bounds finite, '=' and ranged)."""
+    lp = _mixed_bounds_lp(5)
+    P = oracle_mod.Problem(lp)
+    d = P.scaled()
+    rng = np.random.default_rng(6)
+    x0 = 10.0 * rng.standard_normal(lp.n)
+    y0 = 5.0 * rng.standard_normal(lp.m)
+    st = P.init_state(x0, y0)
+    x_want = np.clip(x0, lp.var_lo, lp.var_hi) / d["dc"]
+    lo_f, hi_f = np.isfinite(lp.con_lo), np.isfinite(lp.con_hi)
+    y_proj = np.where(lo_f & hi_f, y0, np.where(lo_f, np.maximum(y0, 0.0),
+                                               np.where(hi_f, np.minimum(y0, 0.0), 0.0)))
+    y_want = y_proj / d["dr"]
+    assert np.allclose(st["x"], x_want, rtol=1e-15, atol=0)
+    assert np.allclose(st["y"], y_want, rtol=1e-15, atol=0)
+    assert np.array_equal(st["xa"], st["x"]) and np.array_equal(st["ya"], st["y"])
+    # every row type and both signs of y0 occur, so each branch is exercised
+    for lo_ok, hi_ok in ((True, True), (True, False), (False, True), (False, False)):
+        rows = (lo_f == lo_ok) & (hi_f == hi_ok)
+        assert np.any(rows & (y0 > 0)) and np.any(rows & (y0 < 0))
+    S = st["state"]
+    assert S.omega == P.omega0 and S.k == 0 and S.t == 0 and S.restarts == 0
+    # no start given: the origin projected (0 inside every box here but the
+    # lower-only boxes [-3, inf) and the free ones contain 0 too)
+    st0 = P.init_state()
+    assert np.array_equal(st0["x"], np.clip(0.0, d["vlo"], d["vhi"]))
+    assert np.all(st0["y"] == 0.0)
