@@ -152,6 +152,8 @@ typedef struct dpdlp_result {
     double omega, eta, sigma_max;
     double setup_seconds, solve_seconds;
     int32_t power_iters, n_checks;    /* Lanczos steps of the sigma_max estimate; checks */
+    int32_t slices_primal, slices_dual;   /* gather slices of each fused step as built    */
+                                          /* (0: unsliced)                              */
 } dpdlp_result;
 
 /* Scalars of the iteration state, for checkpoint / resume and parity tests. */

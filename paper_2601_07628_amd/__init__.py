@@ -69,7 +69,8 @@ class Result(C.Structure):
                 ("obj_dual", C.c_double), ("omega", C.c_double),
                 ("eta", C.c_double), ("sigma_max", C.c_double),
                 ("setup_seconds", C.c_double), ("solve_seconds", C.c_double),
-                ("power_iters", C.c_int32), ("n_checks", C.c_int32)]
+                ("power_iters", C.c_int32), ("n_checks", C.c_int32),
+                ("slices_primal", C.c_int32), ("slices_dual", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1093,6 +1093,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     }
     if (Sd) CHK(build_sliced(P, H.rp, H.ci, H.cp, m, n, Sd, P->sr));   // dual: gathers xbar
     if (Sp) CHK(build_sliced(P, H.cp, H.ri, H.rp, n, m, Sp, P->sc));   // primal: gathers y
+
     if (Sd || Sp) {
         ntmax = std::max(ntmax, std::max(P->sr.ts.n, P->sc.ts.n));
         // the sliced CSR check pass keeps two right-hand sides (2 G doubles)
@@ -1174,6 +1175,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     if (P->sc.S > 0)
         hipLaunchKernelGGL(k_gather_vals<double>, dim3(nblk((int64_t)nnz)), dim3(kBlock), 0, P->s,
                            P->sc.src, P->vt, P->sc.val, (int64_t)nnz);
+
     // A4: step size
     if (P->prm.eta > 0) {
         P->eta = P->prm.eta;
@@ -1197,6 +1199,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         cv(P->v, P->v32, (int64_t)nnz); cv(P->vt, P->vt32, (int64_t)nnz);
         if (P->sr.S > 0) { CHK(dalloc(P, &P->sr.val32, nnz)); cv(P->sr.val, P->sr.val32, (int64_t)nnz); }
         if (P->sc.S > 0) { CHK(dalloc(P, &P->sc.val32, nnz)); cv(P->sc.val, P->sc.val32, (int64_t)nnz); }
+
         CHK(scale_data(P));
     }
     HIPCHK(hipGetLastError());
@@ -1268,6 +1271,11 @@ static int switch_to_fp64(dpdlp_problem *P, bool from_best)
         HIPCHK(hipMemcpyAsync(P->xh, P->xbest, sizeof(double) * P->n, hipMemcpyDeviceToDevice, P->s));
         HIPCHK(hipMemcpyAsync(P->yh, P->ybest, sizeof(double) * P->m, hipMemcpyDeviceToDevice, P->s));
         P->omega = P->fp32_best_omega;
+        // the control kernel measures r in the P-norm of this weight and
+        // starts the next PID step from it, so the device copy follows
+        P->h_ctl->omega = P->omega;
+        HIPCHK(hipMemcpyAsync(&P->ctl->omega, &P->h_ctl->omega, sizeof(double),
+                              hipMemcpyHostToDevice, P->s));
     }
     hipLaunchKernelGGL(k_restart<double>, dim3(nblk(std::max(P->m, P->n))), dim3(kBlock), 0, P->s,
                        P->m, P->n, P->xh, P->yh, P->x, P->xa, P->y, P->ya);
@@ -1411,6 +1419,7 @@ static void fill_result(dpdlp_problem *P, dpdlp_result *r)
     r->omega = P->omega; r->eta = P->eta; r->sigma_max = P->sigma_max;
     r->setup_seconds = P->setup_seconds; r->solve_seconds = P->solve_seconds;
     r->power_iters = P->power_iters; r->n_checks = C.n_checks;
+    r->slices_primal = P->sc.S; r->slices_dual = P->sr.S;
 }
 
 int problem_view(dpdlp_problem *P, ProblemView *o)
