@@ -59,6 +59,14 @@ def load_traffic(kernel: str, workload: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
+def sliced_step(G, step) -> bool:
+    """Whether a fused step runs as a partial-sum kernel plus a combine
+    kernel (gather slices with per-slice partial sums)."""
+    r = G.result(want_xy=False)
+    k = "primal" if step == "primal" else "dual"
+    return r[f"slices_{k}"] > 0
+
+
 def gpu_params(D, **kw):
     p = D.dpdlp_params_default()
     for k, v in kw.items():
@@ -73,6 +81,41 @@ def timed_steps(G, steps, iters_per_step, torch):
         G.iterate(iters_per_step)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_time_to_tol():
+    """The oracle's own solves of c0 and c4 to 1e-4 and 1e-8 on this host
+    (its setup, CSC + scaling + power iteration, timed apart)."""
+    import lpgen
+    import oracle
+    out = {}
+    for name, mk in (("c0", lpgen.config0), ("c4", lpgen.config4)):
+        inst = mk()
+        row = {}
+        for eps in (1e-4, 1e-8):
+            t0 = time.perf_counter()
+            P = oracle.Problem(inst, oracle.Params(eps=eps))
+            prep = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            r = P.solve()
+            el = time.perf_counter() - t0
+            row[f"{eps:g}"] = {"seconds": round(el, 4), "setup_s": round(prep, 3),
+                               "iters": int(r["iters"]), "status": int(r["status"]),
+                               "kkt": max(r["r_primal"], r["r_dual"], r["r_gap"]),
+                               "obj_rel_err": abs(r["obj_p"] - inst.obj_star) / (1 + abs(inst.obj_star))}
+        out[name] = row
+    return out
 
 
 def cpu_baseline(lp, n_iters):
@@ -91,7 +134,7 @@ def cpu_baseline(lp, n_iters):
     P.run(st, n_iters)
     el = time.perf_counter() - t0
     return dict(value=n_iters / el, unit="PDHG iters/s", cores=oracle.num_threads(),
-                kind="oracle",
+                kind="oracle", cpu_model=cpu_model(),
                 sample=(f"{n_iters} FP64 PDHG iterations (checks every 64, as on the GPU) "
                         f"of the oracle on the same config-1 instance after its setup "
                         f"(CSC + 10 Ruiz + Pock-Chambolle, {prep:.1f} s; step size from a "
@@ -170,6 +213,71 @@ def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3, eps_lis
     net.close()
     G.close()
     return out
+
+
+def warmstart_protocol(D, torch, phase, path, n_train=384, n_test=128, epochs=8, lr=1e-3,
+                       eps=1e-8, first=0):
+    """The specified warm-start protocol on the config-4 family, in two
+    phases that fit one GPU session each: "train" solves the 384 training
+    members (FP64, to 1e-8), trains the network and saves its parameters,
+    the reference point and the training record to `path`; "eval" loads
+    them and solves held-out members 384 + first ... from the cold, the
+    family-mean and the network start (trial-judged) to eps, printing one
+    JSON line with the per-member and mean iterations and times."""
+    import numpy as np
+    import lpgen
+    from paper_2601_07628_amd import warmstart as W
+    base = lpgen.config4()
+    G = D.Problem(base, gpu_params(D, eps=1e-8, max_iters=200000),
+                  stream=torch.cuda.current_stream())
+    net = D.WarmStartNet(G, layers=3, stream=torch.cuda.current_stream())
+    if phase == "train":
+        train_i = [lpgen.config4_family(i, base) for i in range(n_train)]
+        t0 = time.perf_counter()
+        sols = W.family_targets(G, train_i, log=log)
+        t_targets = time.perf_counter() - t0
+        ref = W.reference(train_i, sols)
+        net.set_params(W.init_params(3, seed=0))
+        net.set_reference(*ref)
+        t0 = time.perf_counter()
+        hist = W.train(net, train_i, sols, epochs=epochs, lr=lr, log=log)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        rec = {"train_instances": n_train,
+               "targets_converged": int(sum(x is not None for x in sols)),
+               "target_mean_iters": float(np.mean([x["iters"] for x in sols if x is not None])),
+               "targets_seconds": round(t_targets, 2), "train_seconds": round(t_train, 2),
+               "epochs": epochs, "lr": lr, "loss_per_epoch": hist}
+        np.savez(path, params=net.params(), c_ref=ref[0], b_ref=ref[1], x_ref=ref[2],
+                 y_ref=ref[3], record=json.dumps(rec))
+        return rec
+    z = np.load(path, allow_pickle=False)
+    ref = (z["c_ref"], z["b_ref"], z["x_ref"], z["y_ref"])
+    net.set_params(z["params"])
+    net.set_reference(*ref)
+    G.set_params(eps=eps)
+    rows = []
+    for i in range(first, first + n_test):
+        inst = lpgen.config4_family(384 + i, base)
+        row = {"member": 384 + i}
+        for mode in ("cold", "mean", "gnn"):
+            r = W.warm_solve(G, inst, mode, net=net, ref=ref)
+            row[mode] = {"iters": r["iters"], "seconds": round(r["seconds"], 4),
+                         "status": r["status"], "choice": r["choice"],
+                         "first_iter": r["first_iter"]}
+        rows.append(row)
+        log(f"held-out {384 + i}: " + ", ".join(f"{m} {row[m]['iters']}" for m in ("cold", "mean", "gnn")))
+    summ = {}
+    for mode in ("cold", "mean", "gnn"):
+        it = [r[mode]["iters"] for r in rows]
+        sec = [r[mode]["seconds"] for r in rows]
+        summ[mode] = {"mean_iters": round(float(np.mean(it)), 1),
+                      "mean_seconds": round(float(np.mean(sec)), 4),
+                      "converged": int(sum(r[mode]["status"] == D.CONVERGED for r in rows)),
+                      "choices": {c: int(sum(r[mode]["choice"] == c for r in rows))
+                                  for c in ("both", "primal", "dual", "cold")}}
+    return {"eps": eps, "held_out": len(rows), "first_member": 384 + first,
+            "record": json.loads(str(z["record"])), "summary": summ, "members": rows}
 
 
 def layout_stats(D, lp, block, seed, tile_nnz=2048):
@@ -280,10 +388,19 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 256 MiB buffer (device to device), a kernel of "
                          "known size that calibrates the HBM byte counters")
-    ap.add_argument("--workload", choices=("c1", "c2", "lasso"), default="c1",
+    ap.add_argument("--workload", choices=("c1", "c2", "c3", "lasso"), default="c1",
                     help="the instance of the timed steps: c1 (the benchmark), or, for "
-                         "profiling the other paths, c2 (transportation LP) or lasso "
-                         "(the diagonal-QP LASSO); the latter two imply --no-extra --no-cpu")
+                         "profiling the other paths, c2 (transportation LP), c3 (c1 in the "
+                         "FP32-mixed form, held in FP32) or lasso (the diagonal-QP LASSO); "
+                         "these imply --no-extra --no-cpu")
+    ap.add_argument("--ws-protocol", choices=("train", "eval"),
+                    help="instead of the benchmark, run one phase of the specified "
+                         "warm-start protocol on the config-4 family (384 training "
+                         "members, 128 held out), with --ws-file, --ws-eps, --ws-first")
+    ap.add_argument("--ws-file", default="gpurun_out/warmstart_net.npz")
+    ap.add_argument("--ws-eps", type=float, default=1e-8)
+    ap.add_argument("--ws-first", type=int, default=0,
+                    help="first held-out member (0..127) of an eval phase")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark, run the permutation x partition "
                          "ablation on config 1 and its staircase variant")
@@ -301,6 +418,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    if args.ws_protocol:
+        res = warmstart_protocol(D, torch, args.ws_protocol, args.ws_file,
+                                 n_test=min(args.ws_test, 128 - args.ws_first),
+                                 epochs=args.ws_epochs, eps=args.ws_eps, first=args.ws_first)
+        print(json.dumps({"warm_start_protocol": args.ws_protocol,
+                          "kernel_source": kernel_source_hash(), "result": res}), flush=True)
+        return
 
     if args.ablation:
         res = ablation(D, torch, stream, args.steps, args.iters_per_step)
@@ -320,11 +445,13 @@ def main():
         args.no_extra = args.no_cpu = True
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
-    lp = {"c1": lpgen.config1, "c2": lpgen.config2,
+    lp = {"c1": lpgen.config1, "c2": lpgen.config2, "c3": lpgen.config1,
           "lasso": lambda: lpgen.lasso_qp(1_000_000, 500_000, 20, seed=7)}[args.workload]()
     log(f"{args.workload} ready in {time.perf_counter() - t0:.1f} s: {lp.describe()}")
 
-    G = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9), stream=stream)
+    fp32_kw = dict(precision=D.FP32_MIXED, fp32_switch_tol=0.0, fp32_stall_checks=10**6,
+                   fp32_diverge=0.0) if args.workload == "c3" else {}
+    G = D.Problem(lp, gpu_params(D, eps=1e-8, max_iters=10**9, **fp32_kw), stream=stream)
     s = G.scaling()
     G.init()
     setup_s = G.result(want_xy=False)["setup_seconds"]
@@ -350,7 +477,9 @@ def main():
     traffic = load_traffic(dom, args.workload)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "kernel": f"fused_{dom}_step_fp64",
+            "traffic": traffic,
+            "kernel": f"fused_{dom}_step_{'fp32' if fp32_kw else 'fp64'}"
+                      + (" (partial-sum kernel + combine kernel)" if sliced_step(G, dom) else ""),
             "avg_launch_ms": round(avg_ms, 5),
             "alg_bytes_per_launch": fused[dom]["bytes_per_launch"]}
     kern = {k: dict(avg_ms=round(v["total_ms"] / v["launches"], 5), launches=v["launches"],
@@ -577,6 +706,11 @@ def main():
         log(f"CPU baseline: oracle, {args.cpu_iters} iterations on config 1")
         cpu = cpu_baseline(lp, args.cpu_iters)
         log(f"CPU baseline: {cpu['value']:.3f} iters/s on {cpu['cores']} threads")
+        try:
+            cpu["time_to_tol"] = oracle_time_to_tol()
+            log(f"CPU baseline, oracle time to tolerance: {cpu['time_to_tol']}")
+        except Exception as e:            # noqa: BLE001 - reported in the JSON line
+            cpu["time_to_tol_error"] = f"{type(e).__name__}: {e}"
 
     out = {
         "metric": METRIC,
@@ -589,13 +723,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 (FP64 checks)" if fp32_kw else "f64",
         "data": "synthetic (seeded generator; the paper's data sets are not available)",
         "config": {"workload": {
                        "c1": "c1: one GPU's share of a huge LP, m=2,000,000, n=4,000,000, "
                              f"nnz={lp.nnz}, Zipf column degrees, 10% heavy rows, FP64",
                        "c2": f"c2: 3000 x 3000 transportation LP, m=6,000, n=9,000,000, "
                              f"nnz={lp.nnz}, FP64",
+                       "c3": "c3: c1 in the FP32-mixed form (FP32 steps, FP64 checks), "
+                             f"m=2,000,000, n=4,000,000, nnz={lp.nnz}",
                        "lasso": f"LASSO as diagonal QP, 1M samples x 500k features, m={lp.m}, "
                                 f"n={lp.n}, nnz={lp.nnz}, FP64"}[args.workload],
                    "iters_per_step": ips, "check_period": 64, "m": lp.m, "n": lp.n,

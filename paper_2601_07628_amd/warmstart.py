@@ -2,16 +2,20 @@
 
 Everything numerical runs in the library: target solves (the FP64 PDHG
 solver), the network's forward and backward passes and Adam (BF16/FP32 MFMA
-kernels), the KKT judge.  This module only sequences those calls.
+kernels), the trial runs of the judge.  This module only sequences those calls.
 
 Protocol:
   1. solve every training instance with the FP64 solver to eps (targets);
   2. reference point = mean of the training solutions (and of c, b);
   3. train the network (residual on the reference point) with Adam;
   4. for a held-out instance: predict (x0, y0); judge the prediction, its
-     primal part alone and its dual part alone by the relative KKT error of
-     the start point against the cold start (0 clamped into X, 0 projected
-     onto Y); start from the best; if a warm run does not converge within its
+     primal part alone, its dual part alone and the cold start (0 clamped
+     into X, 0 projected onto Y) by a short trial: one check block
+     (check_period iterations) from each, scored by the fixed-point residual
+     r(z) = ||z - T(z)||_P of App. B.2 at the block's last check (all trials
+     start with the same primal weight, so the scores share one norm); the
+     solve starts from the best-scoring point, and the trial iterations are
+     counted in its total; if a warm run does not converge within its
      iteration cap, a cold run takes over.
 """
 from __future__ import annotations
@@ -59,7 +63,7 @@ def family_targets(prob: Problem, instances, log=None) -> List[Optional[dict]]:
     for i, inst in enumerate(instances):
         r = solve_member(prob, inst)
         out.append(dict(x=r["x"], y=r["y"], iters=r["iters"]) if r["status"] == CONVERGED else None)
-        if log and (i + 1) % 64 == 0:
+        if log and (i + 1) % 16 == 0:
             log(f"targets {i + 1}/{len(instances)}")
     return out
 
@@ -100,15 +104,25 @@ def start_kkt(prob: Problem, x0=None, y0=None) -> float:
     return float(max(k[0], k[1], k[2]))
 
 
+def trial_score(prob: Problem, x0=None, y0=None) -> tuple:
+    """One check block from the start point: the fixed-point residual r of
+    its last check (App. B.2) and that check's relative KKT error."""
+    prob.init(x0, y0)
+    prob.iterate(int(prob.params.check_period))
+    last = prob.log()[-1]
+    return float(last["r"]), float(max(last["r_primal"], last["r_dual"], last["r_gap"]))
+
+
 def warm_solve(prob: Problem, inst, mode: str, net: Optional[WarmStartNet] = None,
                ref=None, warm_cap: Optional[int] = None) -> dict:
     """Solve one member from a cold, mean-reference or network start.
 
     Judge: the candidate starts (x0, y0), (x0, cold y), (cold x, y0) and the
-    cold start are scored by the relative KKT error of the point the solver
-    would start from; the best one is used, so a prediction is used only
-    where it beats the cold start.  A warm run that does not converge within
-    warm_cap iterations is followed by a cold run (both are counted)."""
+    cold start each run one check block; the one with the smallest
+    fixed-point residual at its end is solved from the start, so a
+    prediction is used only where its trial beats the cold start's.  The
+    trial iterations count in the total.  A warm run that does not converge
+    within warm_cap iterations is followed by a cold run (both counted)."""
     prob.update_data(inst.c, inst.con_lo, inst.con_hi)
     t0 = time.perf_counter()
     x0 = y0 = None
@@ -117,34 +131,47 @@ def warm_solve(prob: Problem, inst, mode: str, net: Optional[WarmStartNet] = Non
         x0, y0 = net.forward()
     elif mode == "mean":
         x0, y0 = ref[2], ref[3]
-    kw = kc = None
+    total_iters = 0
+    sw = sc = None
     choice = "cold"
     if x0 is not None:
-        kc = start_kkt(prob)
-        cands = {"both": (x0, y0), "primal": (x0, None), "dual": (None, y0)}
-        scores = {k: start_kkt(prob, *v) for k, v in cands.items()}
-        best = min(scores, key=scores.get)
-        kw = scores[best]
-        if kw < kc:
-            choice = best
-            x0, y0 = cands[best]
-        else:
-            x0 = y0 = None
+        cands = {"cold": (None, None), "both": (x0, y0), "primal": (x0, None),
+                 "dual": (None, y0)}
+        scores = {}
+        for k, v in cands.items():
+            scores[k] = trial_score(prob, *v)[0]
+            total_iters += int(prob.params.check_period)
+        choice = min(scores, key=scores.get)
+        sc = scores["cold"]
+        sw = min(v for k, v in scores.items() if k != "cold")
+        x0, y0 = cands[choice]
     fallback = choice == "cold" and mode != "cold"
     saved = prob.params.max_iters
-    total_iters = 0
     warm = x0 is not None or y0 is not None
     if warm and warm_cap:
         prob.set_params(max_iters=warm_cap)
     r = prob.solve(x0, y0)
     total_iters += r["iters"]
+    log = prob.log()
     if r["status"] != CONVERGED and warm:
         prob.set_params(max_iters=saved)
         r = prob.solve()
         total_iters += r["iters"]
+        log = prob.log()
         fallback = True
     prob.set_params(max_iters=saved)
     el = time.perf_counter() - t0
     return dict(mode=mode, iters=int(total_iters), seconds=el, status=int(r["status"]),
-                fallback=fallback, choice=choice, kkt_warm=kw, kkt_cold=kc,
-                obj=r["obj_primal"], kkt=max(r["r_primal"], r["r_dual"], r["r_gap"]))
+                fallback=fallback, choice=choice, judge_warm=sw, judge_cold=sc,
+                obj=r["obj_primal"], kkt=max(r["r_primal"], r["r_dual"], r["r_gap"]),
+                first_iter=first_reach(log, total_iters - int(r["iters"])))
+
+
+def first_reach(log, offset: int, tols=(1e-4, 1e-6, 1e-8)) -> dict:
+    """Iteration count (plus offset) at which the solve's checks first
+    reached each tolerance, from its restart-decision log."""
+    out = {}
+    for tol in tols:
+        out[f"{tol:g}"] = next((offset + int(e["t"]) + 1 for e in log
+                                if max(e["r_primal"], e["r_dual"], e["r_gap"]) <= tol), None)
+    return out

@@ -122,10 +122,16 @@ def test_gnn_forward_and_gradient_match_fp64_reference(D):
                                       tx / dc, ty / dr, act)
         assert abs(loss.sum() - L) <= tol_pred * L
         d_g, d_r = gnn_ref.unpack(g, layers), gnn_ref.unpack(gr, layers)
+        errs = {}
         for name, l in blocks:
             a = d_g[name] if l is None else d_g[name][l]
             b = d_r[name] if l is None else d_r[name][l]
-            assert rel(a, b) < tol_grad, (act is not None, name, l, rel(a, b))
+            errs[name if l is None else f"{name}{l}"] = rel(a, b)
+        print(f"gradient error per block ({'BF16' if act else 'FP64'} activations in the "
+              f"reference): max {max(errs.values()):.3g}; "
+              + ", ".join(f"{k} {v:.2g}" for k, v in errs.items()))
+        for k, v in errs.items():
+            assert v < tol_grad, (act is not None, k, v)
 
 
 def test_gnn_training_reduces_loss_and_is_deterministic(D):
@@ -149,8 +155,9 @@ def test_gnn_training_reduces_loss_and_is_deterministic(D):
 def test_warm_start_prediction_judge_and_solves(D):
     """Held-out members: training brings the predicted start closer to the
     solution than the untrained network (= the mean training solution); the
-    judge keeps a start only when its KKT error beats the cold start's; every
-    run reaches the same optimum.  Iteration counts of cold / mean / network
+    judge keeps a start only when its one-block trial ends with a smaller
+    fixed-point residual than the cold start's trial; every run reaches the
+    same optimum.  Iteration counts of cold / mean / network
     starts are printed (parity unpinned: the speed-up is measured, not
     asserted)."""
     from paper_2601_07628_amd import warmstart as W
@@ -186,7 +193,7 @@ def test_warm_start_prediction_judge_and_solves(D):
         for r in (rm, rg):
             assert abs(r["obj"] - rc["obj"]) <= 1e-6 * (1 + abs(rc["obj"]))
             if not r["fallback"]:
-                assert r["kkt_warm"] < r["kkt_cold"]
+                assert r["judge_warm"] < r["judge_cold"]
     it = {m: float(np.mean([r["iters"] for r in res[m]])) for m in res}
     print(f"prediction error {before:.4g} -> {after:.4g}; mean iterations {it}; "
           f"fallbacks gnn {sum(r['fallback'] for r in res['gnn'])}/{len(test_i)}")
