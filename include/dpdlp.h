@@ -276,6 +276,29 @@ int dpdlp_spmv(dpdlp_problem *prob, int32_t transpose, const double *in, double 
 int dpdlp_kkt(dpdlp_problem *prob, const double *x, const double *y, double tau,
               int32_t mem_kind, double *out5, void *stream);
 
+/* KKT error without allocation, for callers that cannot call hipMalloc
+ * (code under HIP graph capture, tight serving loops).  It needs no
+ * problem handle: the LP (or the diagonal QP of dpdlp_set_objective_diag
+ * when q != NULL) is given in CSR by lp (lp->mem_kind must be
+ * DPDLP_MEM_DEVICE) together with its CSC copy (col_ptr [n+1], row_idx
+ * [nnz], val_csc [nnz]; the same matrix, any row order inside a column).
+ * Every pointer is device memory: x [n], y [m], col_scale [n] or NULL,
+ * q [n] or NULL, and out5 (5 doubles: r_primal, r_dual, r_gap, primal and
+ * dual objective, as dpdlp_kkt).  The primal step of column j in the dual
+ * residual is tau * col_scale[j]^2 (col_scale = NULL: tau), so with D_c from
+ * dpdlp_get_scaling and tau = eta / omega the result is the solver's own
+ * termination measure at (x, y), the one dpdlp_kkt reports.
+ * The call is asynchronous on `stream` and allocates nothing: its partial
+ * sums live in a fixed 3.7 MB device array that each GPU holds until the
+ * process ends, which bounds m and n to [1, 16777216] (INVALID_ARG beyond).
+ * Calls that overlap on one GPU share that array and race.  INVALID_ARG for
+ * NULL pointers, host memory, sizes out of range or tau <= 0; HIP for a
+ * launch failure.                                                        */
+int dpdlp_kkt_noalloc(const dpdlp_csr_lp *lp, const int32_t *col_ptr, const int32_t *row_idx,
+                      const double *val_csc, const double *col_scale, const double *q,
+                      const double *x, const double *y, double tau, double *out5,
+                      void *stream);
+
 /* Scaling vectors D_r [m], D_c [n] (A~ = D_r A D_c) in the original order,
  * eta, sigma_max and omega0 (host pointers; any may be NULL).             */
 int dpdlp_get_scaling(dpdlp_problem *prob, double *dr, double *dc, double *eta,

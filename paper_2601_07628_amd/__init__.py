@@ -109,7 +109,7 @@ EXPORTS = (
     "dpdlp_problem_update_data", "dpdlp_set_params",
     "dpdlp_init", "dpdlp_iterate", "dpdlp_solve", "dpdlp_get_result",
     "dpdlp_state_export", "dpdlp_state_import", "dpdlp_get_log", "dpdlp_spmv",
-    "dpdlp_kkt", "dpdlp_get_scaling", "dpdlp_time_kernel",
+    "dpdlp_kkt", "dpdlp_kkt_noalloc", "dpdlp_get_scaling", "dpdlp_time_kernel",
     "dpdlp_profile_enable", "dpdlp_get_profile", "dpdlp_validate",
     "dpdlp_block_permutation", "dpdlp_build_tiles", "dpdlp_row_bounds", "dpdlp_status_string",
     "dpdlp_last_error", "dpdlp_gnn_create", "dpdlp_gnn_destroy", "dpdlp_gnn_num_params",
@@ -142,6 +142,8 @@ def _load():
         "dpdlp_get_log": ([vp, vp, i32, C.POINTER(i32)], C.c_int),
         "dpdlp_spmv": ([vp, i32, vp, vp, vp], C.c_int),
         "dpdlp_kkt": ([vp, vp, vp, dbl, i32, vp, vp], C.c_int),
+        "dpdlp_kkt_noalloc": ([C.POINTER(CsrLP), vp, vp, vp, vp, vp, vp, vp, dbl, vp, vp],
+                              C.c_int),
         "dpdlp_get_scaling": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
         "dpdlp_time_kernel": ([vp, i32, i32, vp, vp, vp], C.c_int),
         "dpdlp_profile_enable": ([vp, i32], C.c_int),
@@ -328,6 +330,17 @@ def dpdlp_problem_create(lp, params: Optional[Params] = None, stream=None,
     prm = params if params is not None else dpdlp_params_default()
     _check(_lib.dpdlp_problem_create(C.byref(s), C.byref(prm), _stream(stream), C.byref(h)))
     return h
+
+
+def dpdlp_kkt_noalloc(m: int, n: int, csr: dict, csc: dict, x, y, tau: float, out5,
+                      col_scale=None, q=None, stream=None):
+    """KKT at (x, y) of an LP given as device tensors, without allocation:
+    ``csr`` has the host_arrays keys, ``csc`` the keys col_ptr, row_idx, val;
+    x, y, col_scale, q and out5 (5 doubles) are device tensors."""
+    s = _csr_struct(csr, int(m), int(n), MEM_DEVICE)
+    _check(_lib.dpdlp_kkt_noalloc(C.byref(s), _ptr(csc["col_ptr"]), _ptr(csc["row_idx"]),
+                                  _ptr(csc["val"]), _ptr(col_scale), _ptr(q), _ptr(x), _ptr(y),
+                                  float(tau), _ptr(out5), _stream(stream)))
 
 
 def dpdlp_problem_destroy(h):

@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpdlp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["dpdlp_host.cpp", "dpdlp_cost.cpp", "dpdlp_solver.hip", "dpdlp_gnn.hip"]
+SOURCES = ["dpdlp_host.cpp", "dpdlp_cost.cpp", "dpdlp_solver.hip", "dpdlp_gnn.hip",
+           "dpdlp_noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep hipcc from emitting packed FP32 instructions
