@@ -136,7 +136,12 @@ typedef struct dpdlp_params {
                               /* (equal index ranges would put most         */
                               /* nonzeros in one slice); values above 3 are  */
                               /* rejected                                   */
-    int32_t pad1;
+    int32_t gather_sort;      /* sliced steps: store each tile's nonzeros     */
+                              /* sorted by gathered index (products go back  */
+                              /* to their segment order in LDS) -1           */
+                              /* (default): where that cuts the cache lines  */
+                              /* one wave's gathers touch by >= 25%; 0: off; */
+                              /* 1: always                                   */
     double fp32_diverge;      /* FP32 -> FP64 switch when the KKT exceeds    */
                               /* this multiple of the FP32 phase's best (10; */
                               /* 0: off)                                    */

@@ -55,10 +55,10 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("xcd_remap", C.c_int32),
                 ("fp32_switch_tol", C.c_double), ("fp32_stall_checks", C.c_int32),
                 ("gather_slices", C.c_int32), ("use_graphs", C.c_int32),
-                ("perm_order", C.c_int32), ("pad1", C.c_int32), ("fp32_diverge", C.c_double)]
+                ("perm_order", C.c_int32), ("gather_sort", C.c_int32), ("fp32_diverge", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad1"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Result(C.Structure):

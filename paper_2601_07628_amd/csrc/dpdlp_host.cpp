@@ -298,6 +298,60 @@ int64_t count_compact(const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
     return G;
 }
 
+int64_t tile_gather_lines(const std::vector<Tile> &tiles, const hvec<int32_t> &idx,
+                          int32_t line_elems, bool sorted)
+{
+    const int nth = host_threads();
+    const int64_t nt = (int64_t)tiles.size();
+    std::vector<int64_t> part((size_t)nth, 0);
+    run_threads(nth, [&](int th) {
+        std::vector<int32_t> v;
+        for (int64_t t = nt * th / nth; t < nt * (th + 1) / nth; ++t) {
+            const Tile &d = tiles[(size_t)t];
+            v.assign(idx.begin() + d.nnz_begin, idx.begin() + d.nnz_end);
+            if (sorted) std::stable_sort(v.begin(), v.end());
+            for (size_t g = 0; g < v.size(); g += 64) {
+                const size_t e = std::min(v.size(), g + 64);
+                std::vector<int32_t> lines;
+                for (size_t q = g; q < e; ++q) lines.push_back(v[q] / line_elems);
+                std::sort(lines.begin(), lines.end());
+                part[(size_t)th] += std::unique(lines.begin(), lines.end()) - lines.begin();
+            }
+        }
+    });
+    int64_t tot = 0;
+    for (int64_t x : part) tot += x;
+    return tot;
+}
+
+void sort_tiles_by_gather(const std::vector<Tile> &tiles, hvec<int32_t> &idx,
+                          hvec<int32_t> &src, hvec<uint16_t> &pos)
+{
+    pos.resize(idx.size());                  // every entry written below (tiles cover idx)
+    const int nth = host_threads();
+    const int64_t nt = (int64_t)tiles.size();
+    run_threads(nth, [&](int th) {
+        std::vector<int32_t> ord, ti, ts;
+        for (int64_t t = nt * th / nth; t < nt * (th + 1) / nth; ++t) {
+            const Tile &d = tiles[(size_t)t];
+            const int32_t b = d.nnz_begin, cnt = d.nnz_end - d.nnz_begin;
+            ord.resize((size_t)cnt);
+            for (int32_t q = 0; q < cnt; ++q) ord[(size_t)q] = q;
+            std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t c) {
+                return idx[(size_t)(b + a)] < idx[(size_t)(b + c)];
+            });
+            ti.assign(idx.begin() + b, idx.begin() + b + cnt);
+            ts.assign(src.begin() + b, src.begin() + b + cnt);
+            for (int32_t q = 0; q < cnt; ++q) {
+                const int32_t o = ord[(size_t)q];
+                idx[(size_t)(b + q)] = ti[(size_t)o];
+                src[(size_t)(b + q)] = ts[(size_t)o];
+                pos[(size_t)(b + q)] = (uint16_t)o;
+            }
+        }
+    });
+}
+
 void slice_format(const hvec<int32_t> &ptr, const hvec<int32_t> &idx, const hvec<int32_t> &gptr,
                   int32_t nseg, int32_t nidx, int32_t S, int32_t tile_nnz, SlicedHost &out)
 {
@@ -611,6 +665,7 @@ void dpdlp_params_default(dpdlp_params *p)
     p->gather_slices = -1;
     p->use_graphs = 1;
     p->perm_order = 0;
+    p->gather_sort = -1;
     p->fp32_diverge = 10.0;
 }
 

@@ -52,6 +52,20 @@ struct SlicedHost {
     std::vector<uint8_t> mask;
     std::vector<Tile> tiles;
 };
+// Distinct 128-byte lines of the gathered vector (line_elems indices per
+// line) that the tiles' wave instructions touch: each tile's nonzeros in
+// groups of 64 consecutive positions (one wave's load of a tile kernel),
+// counted in storage order, or (sorted = true) after ordering every tile's
+// nonzeros by gathered index.
+int64_t tile_gather_lines(const std::vector<Tile> &tiles, const hvec<int32_t> &idx,
+                          int32_t line_elems, bool sorted);
+// Orders every tile's nonzeros by gathered index (stable), permuting idx
+// and src alike; pos[q] receives, for the nonzero now at q, its position
+// inside its tile before the sort (the tile kernel stores its product
+// there, so the segment sums keep their order).
+void sort_tiles_by_gather(const std::vector<Tile> &tiles, hvec<int32_t> &idx,
+                          hvec<int32_t> &src, hvec<uint16_t> &pos);
+
 // Slices are S contiguous ranges of the gathered index that hold about
 // nnz / S nonzeros each; gptr[nidx + 1] is the gathered dimension's own
 // pointer array (its nonzero counts as prefix sums).

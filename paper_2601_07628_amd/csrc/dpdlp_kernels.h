@@ -15,6 +15,12 @@
 //   3. one thread per segment applies the fused epilogue (projection,
 //      reflection, Halpern, or a residual contribution) with coalesced
 //      vector loads and stores.
+// Where the gathers of a tile hit the same cache lines out of order (rows of
+// a transportation LP, whose columns are strided), the host may store each
+// tile's nonzeros sorted by gathered index, so that one wave's lanes load
+// neighbouring entries together; pos then gives every nonzero's position in
+// the tile's segment order, where its product is stored in LDS, so the
+// segment sums are unchanged.
 // A segment longer than a tile is split into pieces; each piece's workgroup
 // reduces its part and publishes it, and a small follow-up kernel adds the
 // pieces in piece order and runs the epilogue.  The summation order is fixed
@@ -124,6 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op0, const Tile *__restrict_
                                                  const int *__restrict__ seg_ptr,
                                                  const int *__restrict__ idx,
                                                  const typename Op::MT *__restrict__ val,
+                                                 const uint16_t *__restrict__ pos,
                                                  typename Op::AT *__restrict__ carries,
                                                  int remap)
 {
@@ -157,12 +164,21 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op0, const Tile *__restrict_
     // 1a. issue the tile's matrix stream (coalesced, non-temporal)
     int jj[kPer];
     MT aa[kPer];
+    int pp[kPer];             // where each product goes in LDS (gather-sorted tiles)
     if (cnt > 0) {
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int e = min((int)threadIdx.x + q * kBlock, cnt - 1);
             jj[q] = nt_load(idx + nnz0 + e);
             aa[q] = nt_load(val + nnz0 + e);
+        }
+        if (pos) {
+#pragma unroll
+            for (int q = 0; q < kPer; ++q)
+                pp[q] = nt_load(pos + nnz0 + min((int)threadIdx.x + q * kBlock, cnt - 1));
+        } else {
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) pp[q] = threadIdx.x + q * kBlock;
         }
     }
     // 1b. segment pointers to LDS and the epilogue's vector loads
@@ -192,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(Op op0, const Tile *__restrict_
             const int e = threadIdx.x + q * kBlock;
             if (e < cnt) {
 #pragma unroll
-                for (int r = 0; r < NR; ++r) s_prod[r][e] = pv[q][r];
+                for (int r = 0; r < NR; ++r) s_prod[r][pp[q]] = pv[q][r];
             }
         }
     }

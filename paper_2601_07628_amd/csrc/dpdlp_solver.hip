@@ -327,6 +327,7 @@ struct TileSet {
     int *blk2tile = nullptr;        // sliced sets: workgroup -> tile (-1: idle)
     int grid = 0;                   // sliced sets: launch size
     int seg_stride = 0;             // per-slice pointer stride (0 for the compact sliced form)
+    uint16_t *pos = nullptr;        // gather-sorted tiles: product position in the tile
 };
 
 // One format cut into gather slices (the XCD-sliced form of a fused step).
@@ -467,7 +468,8 @@ static void launch_tiles(dpdlp_problem *P, const Op &op, const TileSet &ts, cons
     const int remap = P->prm.xcd_remap ? 1 : 0;
     const int grid = ts.blk2tile ? ts.grid : (remap ? ((ts.n + 7) / 8) * 8 : ts.n);
     hipLaunchKernelGGL(k_tile<Op>, dim3(grid), dim3(kBlock), 0, P->s, op, ts.d, ts.n, ts.blk2tile,
-                       ts.seg_stride, seg_ptr, idx, val, (typename Op::AT *)P->carries, remap);
+                       ts.seg_stride, seg_ptr, idx, val, (const uint16_t *)ts.pos,
+                       (typename Op::AT *)P->carries, remap);
     if (ts.nsplit)
         hipLaunchKernelGGL(k_split_fix<Op>, dim3((ts.nsplit + 63) / 64), dim3(64), 0, P->s, op,
                            ts.splits, ts.nsplit, ts.n, (const typename Op::AT *)P->carries);
@@ -779,6 +781,18 @@ static int build_sliced(dpdlp_problem *P, const hvec<int32_t> &ptr,
     slice_format(ptr, idx, gptr, nseg, nidx, S, P->prm.tile_nnz, sh);
     ss.S = S;
     const size_t nnz = sh.idx.size();
+    // gather-sorted tiles where that cuts the cache lines one wave's gathers
+    // touch by at least a quarter (16 FP64 entries per 128-byte line)
+    hvec<uint16_t> pos;
+    if (nnz && P->prm.gather_sort != 0) {
+        const int64_t l0 = tile_gather_lines(sh.tiles, sh.idx, 16, false);
+        const int64_t l1 = tile_gather_lines(sh.tiles, sh.idx, 16, true);
+        if (P->prm.gather_sort > 0 || (double)l1 <= 0.75 * (double)l0) {
+            sort_tiles_by_gather(sh.tiles, sh.idx, sh.src, pos);
+            CHK(dalloc(P, &ss.ts.pos, nnz));
+            CHK(upload(P, ss.ts.pos, pos.data(), nnz * sizeof(uint16_t)));
+        }
+    }
     CHK(dalloc(P, &ss.ptr, sh.ptr.size()));
     CHK(dalloc(P, &ss.idx, nnz));
     CHK(dalloc(P, &ss.src, nnz));

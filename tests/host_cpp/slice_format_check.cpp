@@ -13,7 +13,11 @@
 //     single windows;
 //   * the combine's position rule (cbase of the 256-segment block plus the
 //     count of earlier segments of the block with that slice bit) stays in
-//     range and adds up to the unsliced segment sum.
+//     range and adds up to the unsliced segment sum;
+//   * gather-sorted tiles (sort_tiles_by_gather): per tile a permutation
+//     that sends every product back to its unsorted position, ascending
+//     indices, and no more touched lines than the storage order
+//     (tile_gather_lines).
 // Built with g++ (AddressSanitizer, UBSan) by tests/test_host_cpu.py.
 #include "dpdlp_internal.h"
 
@@ -118,6 +122,34 @@ int main()
                     ++bad;
                 }
             }
+        // gather-sorted tiles: pos is a permutation of each tile's positions,
+        // the sorted nonzero at q is the one that was at nnz_begin + pos[q],
+        // its indices ascend inside the tile, and its product lands where
+        // the unsorted tile kernel put it (so every segment sum is unchanged)
+        {
+            hvec<int32_t> sidx = sh.idx, ssrc = sh.src;
+            hvec<uint16_t> pos;
+            const int64_t l0 = tile_gather_lines(sh.tiles, sh.idx, 16, false);
+            const int64_t l1 = tile_gather_lines(sh.tiles, sh.idx, 16, true);
+            if (l1 > l0) { std::printf("sorting added lines\n"); ++bad; }
+            sort_tiles_by_gather(sh.tiles, sidx, ssrc, pos);
+            if (pos.size() != sh.idx.size()) { std::printf("pos size\n"); ++bad; continue; }
+            if (tile_gather_lines(sh.tiles, sidx, 16, false) != l1) { std::printf("sorted lines\n"); ++bad; }
+            for (const Tile &t : sh.tiles) {
+                const int cnt = t.nnz_end - t.nnz_begin;
+                std::vector<char> hit((size_t)cnt, 0);
+                for (int q = t.nnz_begin; q < t.nnz_end; ++q) {
+                    const int o = pos[(size_t)q];
+                    if (o < 0 || o >= cnt || hit[(size_t)o]) { std::printf("pos not a permutation\n"); ++bad; break; }
+                    hit[(size_t)o] = 1;
+                    if (sidx[(size_t)q] != sh.idx[(size_t)(t.nnz_begin + o)] ||
+                        ssrc[(size_t)q] != sh.src[(size_t)(t.nnz_begin + o)]) {
+                        std::printf("sorted entry does not match its origin\n");
+                        ++bad;
+                        break;
+                    }
+                    if (q > t.nnz_begin && sidx[(size_t)q] < sidx[(size_t)q - 1]) { std::printf("not sorted\n"); ++bad; break; }
+                }
     }
     // gather_window_bytes: one window (nsample = 1 takes the first) against a
     // brute-force set of lines, on random and on clustered indices
@@ -138,6 +170,8 @@ int main()
         // several windows: the median lies between the smallest and largest
         const double med = gather_window_bytes(idx, nnz, nidx, window, le, 7);
         if (med < 128.0 || med > 128.0 * (double)window) { std::printf("window median %g\n", med); ++bad; }
+            }
+        }
     }
     std::printf(bad ? "FAILED %d\n" : "ok\n", bad);
     return bad != 0;

@@ -248,10 +248,13 @@ def test_iterate_parity_to_tight_tolerance(D, O, name, maker, eps):
     ("transport-60x4000", lambda: lpgen.transport_lp(60, 4000, seed=3), 300),
 ])
 @pytest.mark.parametrize("slices", [8, 16])
-def test_iterate_parity_xcd_sliced(D, O, name, maker, n_iters, slices):
+@pytest.mark.parametrize("gsort", [0, 1])
+def test_iterate_parity_xcd_sliced(D, O, name, maker, n_iters, slices, gsort):
     """The XCD-sliced fused steps (per-slice partial sums added in slice
-    order) change only the summation order."""
-    fixed_run(D, O, maker(), n_iters, gpu_kw=dict(gather_slices=slices))
+    order), with each tile's nonzeros in storage order or sorted by gathered
+    index (products put back in segment order in LDS), change only the
+    summation order."""
+    fixed_run(D, O, maker(), n_iters, gpu_kw=dict(gather_slices=slices, gather_sort=gsort))
 
 
 def test_sliced_fp32_mixed_and_determinism(D, O):
