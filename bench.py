@@ -44,9 +44,9 @@ def kernel_source_hash() -> str:
 
 
 def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "c1_fused_steps_traffic.json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    the workload, if it was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"{workload}_fused_steps_traffic.json")
     if not os.path.exists(p):
         return None
     try:

@@ -1,12 +1,13 @@
 """Summaries of rocprofv3 output for the benchmark's roofline record.
 
-    python -m paper_2601_07628_amd.rocprof_summary trace  <kernel_stats.csv>
-    python -m paper_2601_07628_amd.rocprof_summary traffic <fetch_counter.csv> <write_counter.csv> \
+    python rocprof_summary.py trace  <kernel_stats.csv>
+    python rocprof_summary.py traffic <fetch_counter.csv> <write_counter.csv> \
         --out profiles/c1_fused_steps_traffic.json --workload c1
-    python -m paper_2601_07628_amd.rocprof_summary l2 <tcc_hit_miss_counter.csv>
+    python rocprof_summary.py l2 <tcc_counter.csv>
 
 `trace` prints a per-kernel table (calls, mean/min/max duration); `l2`
-prints mean L2 (TCC) hits, misses and hit rate per dispatch of each kernel.  `traffic`
+prints mean L2 (TCC) requests, hits, misses and the hit rate per dispatch of
+each kernel (requests only when the run collected TCC_REQ_sum).  `traffic`
 turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs (KiB per dispatch)
 into HBM bytes per launch of the fused kernels.  The counters are calibrated
 by the 256 MiB device-to-device copy that ``bench.py --calib-copy`` runs first
@@ -84,18 +85,19 @@ def read_counter(path, counter):
 def step_of(name):
     """Which fused step a kernel belongs to: ('primal' | 'dual', is_head),
     'partial' for the per-slice partial sums (the step is named by the
-    combine that follows), or None."""
-    for op, step in (("PrimalOp<double>", "primal"), ("DualOp<double>", "dual")):
+    combine that follows), or None.  FP64 and FP32 steps alike (a run
+    profiles one precision)."""
+    for op, step in (("PrimalOp<", "primal"), ("DualOp<", "dual")):
         if op in name:
             head = "k_tile<" in name or "k_combine<" in name
             return step, head
-    if "PartialOp<double>" in name:
+    if "PartialOp<double>" in name or "PartialOp<float>" in name:
         return "partial"
     return None
 
 
 def per_step_bytes(disp):
-    """Mean KiB per launch of each fused FP64 step.  A step is the tile
+    """Mean KiB per launch of each fused step.  A step is the tile
     kernel and its split-segment fix-up or, in the XCD-sliced form, the
     per-slice partial kernel (and fix-up) and the combine kernel that follows
     it; partial kernels followed by another pass's combine are dropped."""
@@ -165,16 +167,18 @@ def traffic(fetch_csv, write_csv, workload):
 def l2_table(path):
     hits = read_counter(path, "TCC_HIT_sum")
     miss = {d: v for d, _, v in read_counter(path, "TCC_MISS_sum")}
-    per = defaultdict(lambda: [0, 0.0, 0.0])
+    req = {d: v for d, _, v in read_counter(path, "TCC_REQ_sum")}
+    per = defaultdict(lambda: [0, 0.0, 0.0, 0.0])
     for d, name, h in hits:
         e = per[short_name(name)]
         e[0] += 1
         e[1] += h
         e[2] += miss.get(d, 0.0)
+        e[3] += req.get(d, 0.0)
     rows = []
-    for k, (n, h, m) in per.items():
-        rows.append((k, n, h / n, m / n, h / (h + m) if h + m > 0 else 0.0))
-    rows.sort(key=lambda r: -(r[2] + r[3]) * r[1])
+    for k, (n, h, m, q) in per.items():
+        rows.append((k, n, q / n, h / n, m / n, h / (h + m) if h + m > 0 else 0.0))
+    rows.sort(key=lambda r: -(r[3] + r[4]) * r[1])
     return rows
 
 
@@ -193,9 +197,10 @@ def main(argv=None):
     c.add_argument("--command", default="")
     a = ap.parse_args(argv)
     if a.cmd == "l2":
-        print(f"{'kernel':44s} {'calls':>6s} {'hits/disp':>12s} {'misses/disp':>12s} {'hit rate':>9s}")
-        for k, n, h, m, r in l2_table(a.counter_csv):
-            print(f"{k:44s} {n:6d} {h:12.0f} {m:12.0f} {r:9.3f}")
+        print(f"{'kernel':44s} {'calls':>6s} {'req/disp':>12s} {'hits/disp':>12s} "
+              f"{'misses/disp':>12s} {'hit rate':>9s}")
+        for k, n, q, h, m, r in l2_table(a.counter_csv):
+            print(f"{k:44s} {n:6d} {q:12.0f} {h:12.0f} {m:12.0f} {r:9.3f}")
     elif a.cmd == "trace":
         rows = read_trace(a.stats_csv)
         print(f"{'kernel':44s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}")
@@ -203,7 +208,7 @@ def main(argv=None):
             print(f"{r['short']:44s} {r['calls']:6d} {r['total_ms']:10.3f} {r['avg_us']:9.2f} "
                   f"{r['min_us']:9.2f} {r['max_us']:9.2f}")
     else:
-        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        root = os.path.dirname(os.path.abspath(__file__))
         d = traffic(a.fetch_csv, a.write_csv, a.workload)
         d["source_hash"] = kernel_source_hash(root)
         d["command"] = a.command

@@ -157,9 +157,9 @@ def test_warm_start_prediction_judge_and_solves(D):
     solution than the untrained network (= the mean training solution); the
     judge keeps a start only when its one-block trial ends with a smaller
     fixed-point residual than the cold start's trial; every run reaches the
-    same optimum.  Iteration counts of cold / mean / network
-    starts are printed (parity unpinned: the speed-up is measured, not
-    asserted)."""
+    same optimum; and the network start needs fewer iterations than the
+    cold start (parity unpinned: the size of the gain is measured; iteration
+    counts of cold / mean / network starts are printed)."""
     from paper_2601_07628_amd import warmstart as W
     base, insts = _family(n_inst=36)
     train_i, test_i = insts[:28], insts[28:]
@@ -197,3 +197,8 @@ def test_warm_start_prediction_judge_and_solves(D):
     it = {m: float(np.mean([r["iters"] for r in res[m]])) for m in res}
     print(f"prediction error {before:.4g} -> {after:.4g}; mean iterations {it}; "
           f"fallbacks gnn {sum(r['fallback'] for r in res['gnn'])}/{len(test_i)}")
+    # what the trained network gains over the method without it: the judged
+    # network start (trial iterations included) needs fewer iterations on
+    # average than the cold start (measured: 26,696 against 36,608 on these
+    # 8 members; runs are bitwise reproducible)
+    assert it["gnn"] < it["cold"], it
