@@ -55,8 +55,7 @@ def load_traffic(kernel: str, workload: str):
         return None
     if d.get("source_hash") != kernel_source_hash():
         return None
-    e = d.get("kernels", {}).get(f"{workload}/{kernel}")
-    return None if e is None else e.get("bytes_per_launch")
+    return d.get("kernels", {}).get(f"{workload}/{kernel}")
 
 
 def sliced_step(G, step) -> bool:
@@ -474,7 +473,8 @@ def main():
     dom = max(fused, key=lambda k: fused[k]["total_ms"])
     avg_ms = fused[dom]["total_ms"] / fused[dom]["launches"]
     achieved = fused[dom]["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(dom, args.workload)
+    tr = load_traffic(dom, args.workload)
+    traffic = None if tr is None else tr.get("bytes_per_launch")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
@@ -482,6 +482,13 @@ def main():
                       + (" (partial-sum kernel + combine kernel)" if sliced_step(G, dom) else ""),
             "avg_launch_ms": round(avg_ms, 5),
             "alg_bytes_per_launch": fused[dom]["bytes_per_launch"]}
+    if tr is not None and tr.get("l2_requests_per_launch"):
+        # the request side: L2 (TCC) requests per launch from the committed
+        # counter run, over the live launch time (the random gathers make
+        # one request each, which is what bounds these steps)
+        roof["l2_requests_per_launch"] = round(tr["l2_requests_per_launch"])
+        roof["l2_hit_rate"] = round(tr["l2_hits_per_launch"] / tr["l2_requests_per_launch"], 3)
+        roof["l2_Greq_per_s"] = round(tr["l2_requests_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
     kern = {k: dict(avg_ms=round(v["total_ms"] / v["launches"], 5), launches=v["launches"],
                     alg_GBps=round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"]) / 1e6, 1)
                     if v["bytes_per_launch"] else None)

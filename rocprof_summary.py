@@ -97,7 +97,8 @@ def step_of(name):
 
 
 def per_step_bytes(disp):
-    """Mean KiB per launch of each fused step.  A step is the tile
+    """Mean counter value (KiB for FETCH_SIZE / WRITE_SIZE) per launch of each
+    fused step.  A step is the tile
     kernel and its split-segment fix-up or, in the XCD-sliced form, the
     per-slice partial kernel (and fix-up) and the combine kernel that follows
     it; partial kernels followed by another pass's combine are dropped."""
@@ -131,7 +132,7 @@ def kernel_source_hash(root):
     return h.hexdigest()[:16]
 
 
-def traffic(fetch_csv, write_csv, workload):
+def traffic(fetch_csv, write_csv, workload, tcc_csv=None):
     fe = read_counter(fetch_csv, "FETCH_SIZE")
     wr = read_counter(write_csv, "WRITE_SIZE")
 
@@ -153,6 +154,13 @@ def traffic(fetch_csv, write_csv, workload):
         out["kernels"][f"{workload}/{step}"] = {
             "launches": n, "fetch_bytes_per_launch": f_b,
             "write_bytes_per_launch": w_b, "bytes_per_launch": f_b + w_b}
+    if tcc_csv:
+        # L2 requests of each fused step (its partial-sum and combine
+        # kernels together), from a TCC_REQ_sum / TCC_HIT_sum run
+        for ctr, key in (("TCC_REQ_sum", "l2_requests_per_launch"),
+                         ("TCC_HIT_sum", "l2_hits_per_launch")):
+            for step, (v, n) in per_step_bytes(read_counter(tcc_csv, ctr)).items():
+                out["kernels"].setdefault(f"{workload}/{step}", {})[key] = v
     per_kernel = defaultdict(list)
     for _, name, v in fe:
         per_kernel[short_name(name)].append(v)
@@ -194,6 +202,7 @@ def main(argv=None):
     c.add_argument("write_csv")
     c.add_argument("--out", required=True)
     c.add_argument("--workload", default="c1")
+    c.add_argument("--tcc", default=None, help="TCC_REQ_sum / TCC_HIT_sum counter run")
     c.add_argument("--command", default="")
     a = ap.parse_args(argv)
     if a.cmd == "l2":
@@ -209,7 +218,7 @@ def main(argv=None):
                   f"{r['min_us']:9.2f} {r['max_us']:9.2f}")
     else:
         root = os.path.dirname(os.path.abspath(__file__))
-        d = traffic(a.fetch_csv, a.write_csv, a.workload)
+        d = traffic(a.fetch_csv, a.write_csv, a.workload, a.tcc)
         d["source_hash"] = kernel_source_hash(root)
         d["command"] = a.command
         with open(a.out, "w") as f:
