@@ -400,6 +400,11 @@ def main():
     ap.add_argument("--ws-eps", type=float, default=1e-8)
     ap.add_argument("--ws-first", type=int, default=0,
                     help="first held-out member (0..127) of an eval phase")
+    ap.add_argument("--c1-tol", type=float, default=None,
+                    help="instead of the benchmark, solve c1 to this tolerance in FP64 and "
+                         "in FP32-mixed form (each capped at --c1-cap seconds) and print the "
+                         "times, iterations and KKT reached")
+    ap.add_argument("--c1-cap", type=float, default=180.0)
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark, run the permutation x partition "
                          "ablation on config 1 and its staircase variant")
@@ -423,6 +428,35 @@ def main():
                                  n_test=min(args.ws_test, 128 - args.ws_first),
                                  epochs=args.ws_epochs, eps=args.ws_eps, first=args.ws_first)
         print(json.dumps({"warm_start_protocol": args.ws_protocol,
+                          "kernel_source": kernel_source_hash(), "result": res}), flush=True)
+        return
+
+    if args.c1_tol:
+        lp1 = lpgen.config1()
+        res = {}
+        for name, kw in (("fp64", {}), ("fp32_mixed", {"precision": D.FP32_MIXED})):
+            Gt = D.Problem(lp1, gpu_params(D, eps=args.c1_tol, max_iters=10**9,
+                                           time_limit=args.c1_cap, **kw), stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = Gt.solve()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            lg = Gt.log()
+            kk = [max(e["r_primal"], e["r_dual"], e["r_gap"]) for e in lg]
+            res[name] = {"seconds": round(el, 3), "iters": int(r["iters"]),
+                         "status": D.dpdlp_status_string(r["status"]),
+                         "kkt": max(r["r_primal"], r["r_dual"], r["r_gap"]),
+                         "fp32_iters": int(r["fp32_iters"]), "restarts": int(r["restarts"]),
+                         "setup_s": round(r["setup_seconds"], 3),
+                         "obj_rel_err": abs(r["obj_primal"] - lp1.obj_star) / (1 + abs(lp1.obj_star)),
+                         "first_iter": {f"{t:g}": next((int(e["t"]) + 1 for e, v in zip(lg, kk)
+                                                        if v <= t), None)
+                                        for t in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8)},
+                         "omega_range": [min(e["omega"] for e in lg), max(e["omega"] for e in lg)]}
+            log(f"c1 to {args.c1_tol:g}, {name}: {res[name]}")
+            Gt.close()
+        print(json.dumps({"c1_time_to_tol": args.c1_tol, "cap_s": args.c1_cap,
                           "kernel_source": kernel_source_hash(), "result": res}), flush=True)
         return
 
