@@ -439,7 +439,15 @@ def main():
                                            time_limit=args.c1_cap, **kw), stream=stream)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = Gt.solve()
+            Gt.init()
+            while True:                      # in blocks, with a progress line each
+                Gt.iterate(100 * 64)
+                r = Gt.result(want_xy=False)
+                log(f"c1 {name}: {r['iters']} iterations, KKT "
+                    f"{max(r['r_primal'], r['r_dual'], r['r_gap']):.3e}, "
+                    f"{time.perf_counter() - t0:.1f} s")
+                if r["status"] != D.RUNNING:
+                    break
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             lg = Gt.log()
