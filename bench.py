@@ -117,6 +117,19 @@ def oracle_time_to_tol():
     return out
 
 
+def oracle_objective(name):
+    """The oracle's objective at relative KKT 1e-8 for an instance without a
+    constructed optimum (tests/golden/oracle_objectives.json, written by
+    tests/golden/make_oracle_objectives.py), or None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                        "oracle_objectives.json")
+    try:
+        with open(path) as f:
+            return json.load(f)[name]["obj_primal"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(lp, n_iters):
     """The FP64 oracle on the same instance, timed on this host."""
     import oracle
@@ -615,13 +628,53 @@ def main():
         r64 = time_to_tol(D, inst, torch)
         r32 = time_to_tol(D, inst, torch, precision=D.FP32_MIXED)
         # error of each result against the constructed optimum (the FP64
-        # oracle reaches it to the same tolerance; parity tests pin that)
+        # oracle reaches it to the same tolerance; parity tests pin that),
+        # or, for the transportation LP, against the oracle's own objective
+        # at 1e-8 (a stored value written by a script that runs the oracle)
+        if inst.obj_star is not None:
+            ref, kind = inst.obj_star, "obj_constructed"
+        else:
+            ref, kind = oracle_objective(name), "obj_oracle_1e-8"
         for rr in (r64, r32):
             for v in rr.values():
-                v["obj_rel_err"] = abs(v["obj"] - inst.obj_star) / (1.0 + abs(inst.obj_star))
-        extra[f"time_to_tol_{name}"] = {"fp64": r64, "fp32_mixed": r32,
-                                         "obj_constructed": inst.obj_star}
+                if ref is not None:
+                    v["obj_rel_err"] = abs(v["obj"] - ref) / (1.0 + abs(ref))
+        extra[f"time_to_tol_{name}"] = {"fp64": r64, "fp32_mixed": r32, kind: ref}
         log(f"time-to-tolerance {name}: {extra[f'time_to_tol_{name}']}")
+
+    def staircase_ttt():
+        # config 1's size and nonzeros per column with staircase structure
+        # (local gathers): it reaches 1e-8 in about 50k iterations, so there
+        # FP32-mixed and FP64 compare at 1e-8 on a 40M-nonzero instance (one
+        # solve each, 90 s cap)
+        lps = lpgen.config1_staircase()
+        out = {}
+        for name, kw in (("fp64", {}), ("fp32_mixed", {"precision": D.FP32_MIXED})):
+            Gt = D.Problem(lps, gpu_params(D, eps=1e-8, max_iters=10**9, time_limit=90.0, **kw),
+                           stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Gt.init()
+            while True:                      # in blocks, with a progress line each
+                Gt.iterate(100 * 64)
+                r = Gt.result(want_xy=False)
+                if r["status"] != D.RUNNING:
+                    break
+                log(f"staircase {name}: {r['iters']} iterations, KKT "
+                    f"{max(r['r_primal'], r['r_dual'], r['r_gap']):.2e}")
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[name] = {"seconds": round(el, 3), "iters": int(r["iters"]),
+                         "status": D.dpdlp_status_string(r["status"]),
+                         "kkt": max(r["r_primal"], r["r_dual"], r["r_gap"]),
+                         "obj_rel_err": abs(r["obj_primal"] - lps.obj_star) / (1.0 + abs(lps.obj_star)),
+                         "fp32_iters": int(r["fp32_iters"]),
+                         "setup_s": round(r["setup_seconds"], 3)}
+            Gt.close()
+        out["instance"] = (f"staircase LP, m={lps.m}, n={lps.n}, nnz={lps.nnz}, "
+                           "2000 stages, 10 nonzeros per column")
+        extra["time_to_1e-8_staircase"] = out
+        log(f"staircase time to 1e-8: {out}")
 
     def c1_ttt():
         out = {}
@@ -719,8 +772,10 @@ def main():
             guarded(f"fp64_gather_slices_{S}", lambda S=S: sliced(S))
         guarded("fp32_mixed_c1", fp32)
         guarded("c2_fp64", c2_rate)
-        for name, mk in (("c0", lpgen.config0), ("c4", lpgen.config4)):
+        for name, mk in (("c0", lpgen.config0), ("c4", lpgen.config4), ("c2", lpgen.config2)):
             guarded(f"time_to_tol_{name}", lambda name=name, mk=mk: ttt(name, mk))
+        if not args.no_c1_ttt:
+            guarded("time_to_1e-8_staircase", staircase_ttt)
         if not args.no_c1_ttt:
             guarded("time_to_1e-4_c1", c1_ttt)
         guarded("lasso_qp_fp64", lasso)

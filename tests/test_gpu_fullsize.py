@@ -117,3 +117,35 @@ def test_lasso_qp_fullsize_parity(D):
     1M samples x 500k features, 22.9M nonzeros; default parameters),
     70 iterations: one full check block plus the next check."""
     _fullsize(D, "lasso", 70, -1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_c2_solves_to_1e8_at_the_oracle_objective(D, precision):
+    """The transportation LP solved to relative KKT 1e-8 (App. B.4) with the
+    default parameters, in FP64 and in FP32-mixed form, reaches the FP64
+    oracle's objective at 1e-8 (tests/golden/oracle_objectives.json, written
+    by make_oracle_objectives.py from the oracle alone).  Both points have a
+    relative gap and relative residuals of at most 1e-8, so their objectives
+    differ by a few times 1e-8 (1 + |obj|) at most; the bar is 1e-7."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_objectives.json")) as f:
+        ref = json.load(f)["c2"]
+    lp = lpgen.config2()
+    prm = D.dpdlp_params_default()
+    prm.eps = 1e-8
+    if precision == "fp32_mixed":
+        prm.precision = D.FP32_MIXED
+    G = D.Problem(lp, prm)
+    r = G.solve()
+    assert r["status"] == D.CONVERGED
+    assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= 1e-8
+    err = abs(r["obj_primal"] - ref["obj_primal"]) / (1 + abs(ref["obj_primal"]))
+    print(f"c2 {precision}: {r['iters']} iterations ({r['fp32_iters']} in FP32), objective "
+          f"{r['obj_primal']:.10g} against the oracle's {ref['obj_primal']:.10g} "
+          f"(relative {err:.2e})")
+    assert err <= 1e-7, err
+    if precision == "fp64":
+        # the same method to the same tolerance (the step sizes differ
+        # slightly: Lanczos on the GPU, power iteration in the oracle)
+        assert abs(r["iters"] - ref["iters"]) <= 0.25 * ref["iters"], (r["iters"], ref["iters"])
