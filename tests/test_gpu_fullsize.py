@@ -149,3 +149,32 @@ def test_c2_solves_to_1e8_at_the_oracle_objective(D, precision):
         # the same method to the same tolerance (the step sizes differ
         # slightly: Lanczos on the GPU, power iteration in the oracle)
         assert abs(r["iters"] - ref["iters"]) <= 0.25 * ref["iters"], (r["iters"], ref["iters"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_c1_solves_to_1e4_at_the_oracle_objective(D, precision):
+    """c1, and c3 (its FP32-mixed form), solved to relative KKT 1e-4 with the
+    default parameters, reach the objective of the oracle's own 1e-4 solve
+    (tests/golden/oracle_objectives.json).  Two points at 1e-4 each have a
+    relative gap and residuals of at most 1e-4, so the bar is the other
+    solve tests' 10 eps (1 + |obj|); measured: 2.3e-6 (FP64, the same 7,296
+    iterations as the oracle) and 2.5e-4 (FP32-mixed)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_objectives.json")) as f:
+        ref = json.load(f)["c1"]
+    lp = lpgen.config1()
+    prm = D.dpdlp_params_default()
+    prm.eps = 1e-4
+    prm.time_limit = 60.0
+    if precision == "fp32_mixed":
+        prm.precision = D.FP32_MIXED
+    G = D.Problem(lp, prm)
+    r = G.solve()
+    assert r["status"] == D.CONVERGED
+    assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= 1e-4
+    err = abs(r["obj_primal"] - ref["obj_primal"]) / (1 + abs(ref["obj_primal"]))
+    print(f"c1 {precision} to 1e-4: {r['iters']} iterations ({r['fp32_iters']} in FP32), "
+          f"objective {r['obj_primal']:.10g} against the oracle's {ref['obj_primal']:.10g} "
+          f"(relative {err:.2e})")
+    assert err <= 10 * 1e-4, err
