@@ -544,6 +544,28 @@ def main():
         roof["l2_requests_per_launch"] = round(tr["l2_requests_per_launch"])
         roof["l2_hit_rate"] = round(tr["l2_hits_per_launch"] / tr["l2_requests_per_launch"], 3)
         roof["l2_Greq_per_s"] = round(tr["l2_requests_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
+    # the gather side, measured: the step's nnz random gathers alone, in its
+    # slice pattern (dpdlp_time_gather), against the whole fused step
+    # (gathers, matrix stream, partial sums, combine and epilogue)
+    probe = {}
+    prec = D.FP32_MIXED if fp32_kw else D.FP64
+    for step, nvec, S in (("primal", lp.m, res["slices_primal"]), ("dual", lp.n, res["slices_dual"])):
+        if S > 0 and step in fused:
+            try:
+                pg = D.dpdlp_time_gather(nvec, S, lp.nnz, precision=prec, reps=20, stream=stream)
+            except Exception as e:        # noqa: BLE001 - reported in the JSON line
+                probe[f"{step}_error"] = f"{type(e).__name__}: {e}"
+                continue
+            st_ms = fused[step]["total_ms"] / fused[step]["launches"]
+            probe[step] = {"slices": int(S), "gathers": int(lp.nnz),
+                           "probe_ms": round(pg["avg_ms"], 5),
+                           "probe_Ggathers_per_s": round(pg["gathers_per_s"] / 1e9, 1),
+                           "step_ms": round(st_ms, 5),
+                           "step_Ggathers_per_s": round(lp.nnz / (st_ms * 1e-3) / 1e9, 1),
+                           "frac": round(pg["avg_ms"] / st_ms, 3)}
+            log(f"gather probe, {step} pattern: {probe[step]}")
+    if probe:
+        roof["gather_probe"] = probe
     kern = {k: dict(avg_ms=round(v["total_ms"] / v["launches"], 5), launches=v["launches"],
                     alg_GBps=round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"]) / 1e6, 1)
                     if v["bytes_per_launch"] else None)

@@ -309,6 +309,25 @@ int dpdlp_kkt_noalloc(const dpdlp_csr_lp *lp, const int32_t *col_ptr, const int3
 int dpdlp_get_scaling(dpdlp_problem *prob, double *dr, double *dc, double *eta,
                       double *sigma_max, double *omega0, void *stream);
 
+/* Random-gather rate probe: the ceiling for the gathers of the XCD-sliced
+ * fused steps (Sec. 3.1's partition of the gathered vector, one slice per
+ * XCD).  Gathers n_gathers entries of a device vector of n_vec elements
+ * (precision DPDLP_FP64: double, DPDLP_FP32_MIXED: float) at uniform random
+ * indices, 2048 per workgroup of 256 threads as in one tile, each
+ * workgroup's indices inside one of `slices` equal slices of the vector
+ * (slice s on XCD s % 8, an XCD's slices one after another), and sums them
+ * per thread.  *avg_ms receives the mean time of one pass over `reps`
+ * timed launches (HIP events on `stream`, after one warm-up launch);
+ * *gathers_per_s (may be NULL) n_gathers divided by it.  The indices come
+ * from a splitmix64 stream started at `seed`.  The call allocates and
+ * frees its own device buffers (4 n_gathers + n_vec elements) and
+ * synchronizes.  INVALID_ARG unless slices is a multiple of 8 up to 64,
+ * slices <= n_vec < 2^31, 1 <= n_gathers < 2^31 and reps >= 1; OOM or HIP
+ * on a device failure.                                                    */
+int dpdlp_time_gather(int64_t n_vec, int32_t slices, int64_t n_gathers, int32_t precision,
+                      int32_t reps, uint64_t seed, void *stream, double *avg_ms,
+                      double *gathers_per_s);
+
 /* Time one kernel class over `reps` launches on `stream` with HIP events:
  * which = 0 fused primal step, 1 fused dual step, 2 CSR SpMV, 3 CSC SpMV.
  * *avg_ms receives the mean duration; *bytes the algorithmic bytes moved per

@@ -117,6 +117,7 @@ EXPORTS = (
     "dpdlp_gnn_set_instance", "dpdlp_gnn_forward", "dpdlp_gnn_backward",
     "dpdlp_gnn_adam_step", "dpdlp_gnn_gemm_test", "dpdlp_cost_params_default",
     "dpdlp_cost_step", "dpdlp_grid_select", "dpdlp_auto_devices", "dpdlp_set_objective_diag",
+    "dpdlp_time_gather",
 )
 
 
@@ -146,6 +147,7 @@ def _load():
                               C.c_int),
         "dpdlp_get_scaling": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
         "dpdlp_time_kernel": ([vp, i32, i32, vp, vp, vp], C.c_int),
+        "dpdlp_time_gather": ([i64, i32, i64, i32, i32, u64, vp, vp, vp], C.c_int),
         "dpdlp_profile_enable": ([vp, i32], C.c_int),
         "dpdlp_get_profile": ([vp, vp, vp, vp], C.c_int),
         "dpdlp_validate": ([C.POINTER(CsrLP)], C.c_int),
@@ -314,6 +316,16 @@ def dpdlp_auto_devices(m: int, n: int, nnz: int, counts=(1, 2, 4, 8),
     _check(_lib.dpdlp_auto_devices(m, n, nnz, _ptr(cnt), cnt.size, C.byref(p), C.byref(nd),
                                    C.byref(r), C.byref(c), C.byref(t)))
     return dict(ndev=nd.value, R=r.value, C=c.value, t_step=t.value)
+
+
+def dpdlp_time_gather(n_vec: int, slices: int, n_gathers: int, precision: int = 0,
+                      reps: int = 20, seed: int = 1, stream=None) -> dict:
+    """Random-gather rate probe (the sliced steps' gather pattern): mean ms
+    per pass of n_gathers gathers and the gathers per second."""
+    ms, rate = C.c_double(), C.c_double()
+    _check(_lib.dpdlp_time_gather(n_vec, slices, n_gathers, precision, reps, seed,
+                                  _stream(stream), C.byref(ms), C.byref(rate)))
+    return dict(avg_ms=ms.value, gathers_per_s=rate.value)
 
 
 def dpdlp_problem_create(lp, params: Optional[Params] = None, stream=None,

@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libdpdlp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["dpdlp_host.cpp", "dpdlp_cost.cpp", "dpdlp_solver.hip", "dpdlp_gnn.hip",
-           "dpdlp_noalloc.hip"]
+           "dpdlp_noalloc.hip", "dpdlp_probe.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep hipcc from emitting packed FP32 instructions

@@ -591,3 +591,19 @@ def test_fp32_mixed_iterates_against_fp64_oracle(D, O, name, maker):
     errs = {k: rel(gs[k], st[k]) for k in ("xh", "yh")}
     print(f"{name}: FP32-mixed vs FP64 oracle after 64 iterations: {errs}")
     assert max(errs.values()) <= 1e-5, errs
+
+
+def test_time_gather_probe(D):
+    """The random-gather probe that bench.py sets beside the fused steps:
+    it runs in both precisions and slice counts, reports a positive rate,
+    and rejects bad arguments with a message."""
+    for prec in (D.FP64, D.FP32_MIXED):
+        for S in (8, 16):
+            r = D.dpdlp_time_gather(1 << 20, S, 3_000_001, precision=prec, reps=3)
+            assert r["avg_ms"] > 0 and r["gathers_per_s"] > 1e9, (prec, S, r)
+    for bad in (dict(n_vec=1 << 20, slices=12, n_gathers=1000),
+                dict(n_vec=7, slices=8, n_gathers=1000),
+                dict(n_vec=1 << 20, slices=8, n_gathers=0)):
+        with pytest.raises(D.DpdlpError, match="dpdlp_time_gather") as e:
+            D.dpdlp_time_gather(**bad)
+        assert e.value.code == D.E_INVALID_ARG
