@@ -83,14 +83,28 @@ def timed_steps(G, steps, iters_per_step, torch):
 
 
 def cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo names it (virtual machines may report
+    only the vendor line), with its family / model / stepping numbers and
+    the logical CPUs visible to this process."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v.strip()
+                if not line.strip() and info:
+                    break
     except OSError:
         pass
-    return "unknown"
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return (f"{info.get('model name', 'unknown')} (family {info.get('cpu family', '?')}, "
+            f"model {info.get('model', '?')}, stepping {info.get('stepping', '?')}; "
+            f"{os.cpu_count()} logical CPUs, {avail} available to this process)")
 
 
 def oracle_time_to_tol():
