@@ -353,6 +353,24 @@ def test_edge_cases_empty_rows_cols_free_rows(D, O, slices):
     assert abs(r["obj_primal"] - o["obj_p"]) < 1e-8
 
 
+def test_matrix_without_nonzeros(D, O):
+    """A = 0 (3 rows, none of them binding, one an equality 0 = 0): a
+    box-only LP, x_j = l_j where c_j > 0 and u_j where c_j < 0; tiles of
+    empty segments only.  Iterates against the oracle, then the solve
+    against the closed form."""
+    rng = np.random.default_rng(12)
+    n = 40
+    c = rng.standard_normal(n)
+    lo, hi = -rng.uniform(0, 2, n), rng.uniform(0, 2, n)
+    lp = lpgen.from_dense(np.zeros((3, n)), c, [-np.inf, -1.0, 0.0], [np.inf, 1.0, 0.0], lo, hi)
+    assert lp.nnz == 0
+    fixed_run(D, O, lp, 150)
+    r = D.Problem(lp, gpu_params(D, eps=1e-10)).solve()
+    assert r["status"] == D.CONVERGED
+    assert np.abs(r["x"] - np.where(c > 0, lo, hi)).max() <= 1e-9
+    assert abs(r["obj_primal"] - np.sum(np.where(c > 0, c * lo, c * hi))) <= 1e-9
+
+
 @pytest.mark.parametrize("slices", [-1, 8])
 def test_single_row_and_single_column(D, O, slices):
     """One row of 5000 nonzeros and one column of 4000 (split over tiles;
