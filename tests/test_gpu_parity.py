@@ -567,12 +567,15 @@ def test_bad_parameters_are_rejected(D, kw, msg):
     assert e.value.code == D.E_INVALID_ARG
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(precision=1), dict(gather_slices=8)])
-def test_graph_replay_matches_eager_bitwise(D, kw):
+@pytest.mark.parametrize("kw,qp", [(dict(), False), (dict(precision=1), False),
+                                   (dict(gather_slices=8), False), (dict(), True),
+                                   (dict(precision=1, gather_slices=8), True)])
+def test_graph_replay_matches_eager_bitwise(D, kw, qp):
     """Runs between checks replayed as one HIP graph give bitwise the same
     solve as eager launches (dozens of replays with restarts, checks and host
-    synchronizations between them)."""
-    lp = lpgen.config4()
+    synchronizations between them), for the LP and for the diagonal QP's
+    primal step (FP64 unsliced, FP32-mixed sliced)."""
+    lp = lpgen.constructed_qp(2000, 4000, 1000, 5, seed=21) if qp else lpgen.config4()
     outs = []
     for graphs in (0, 1):
         G = D.Problem(lp, gpu_params(D, use_graphs=graphs, **kw))
