@@ -93,8 +93,9 @@ typedef struct dpdlp_params {
                               /* permutation (Sec. 4.2); 0: no permutation   */
     int32_t tile_nnz;         /* nonzeros per workgroup tile (Sec. 4.3 at CU */
                               /* granularity), max 2048; 0 = automatic: the  */
-                              /* power of two in [256, 2048] nearest above   */
-                              /* nnz / 1280 (one round of 5 resident         */
+                              /* power of two in [256, 2048] nearest to      */
+                              /* nnz / 800 on a log scale (about 800 tiles   */
+                              /* per step, within one round of 5 resident    */
                               /* workgroups on each of the 256 CUs)          */
     uint64_t perm_seed;       /* seed of the block permutation               */
     int32_t precision;        /* DPDLP_FP64 or DPDLP_FP32_MIXED              */

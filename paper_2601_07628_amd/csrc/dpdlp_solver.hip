@@ -1025,13 +1025,13 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     std::unique_ptr<dpdlp_problem> guard(P);
     if (params) P->prm = *params; else dpdlp_params_default(&P->prm);
     if (P->prm.tile_nnz <= 0) {
-        // automatic: the smallest power of two (256..2048) that keeps the
-        // tiles within one round of resident workgroups (256 CUs x 5), so
-        // that a small problem's tiles all run at once
-        const int64_t nz = lp.row_ptr[lp.m];
-        int64_t tn = nz / (256 * 5);
+        // automatic: the power of two (256..2048) nearest, on a log scale,
+        // to nnz / 800, i.e. about 800 tiles per step where the problem is
+        // small enough: fewer tiles than one round of resident workgroups
+        // (256 CUs x 5), each long enough to hide its memory round trips
+        const double tn = (double)lp.row_ptr[lp.m] / 800.0;
         int32_t p2 = 256;
-        while (p2 < tn && p2 < kTileNnzMax) p2 <<= 1;
+        while (p2 < kTileNnzMax && tn > (double)p2 * 1.4142135623730951) p2 <<= 1;
         P->prm.tile_nnz = p2;
     }
     if (P->prm.tile_nnz > kTileNnzMax) P->prm.tile_nnz = kTileNnzMax;
