@@ -423,7 +423,7 @@ def main():
                     help="instead of the benchmark, run one phase of the specified "
                          "warm-start protocol on the config-4 family (384 training "
                          "members, 128 held out), with --ws-file, --ws-eps, --ws-first")
-    ap.add_argument("--ws-file", default="gpurun_out/warmstart_net.npz")
+    ap.add_argument("--ws-file", default="warmstart_net.npz")
     ap.add_argument("--ws-eps", type=float, default=1e-8)
     ap.add_argument("--ws-first", type=int, default=0,
                     help="first held-out member (0..127) of an eval phase")
