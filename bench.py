@@ -196,7 +196,8 @@ def time_to_tol(D, lp, torch, reps=5, **kw):
 def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3, eps_list=(1e-6, 1e-8)):
     """Config-4 family: targets from the FP64 solver, network trained on the
     GPU, held-out members solved cold / from the mean solution / from the
-    network (with the KKT-judged fallback) to 1e-6 and 1e-8."""
+    network (candidates judged by a one-check-block trial, with the cold
+    fallback) to 1e-6 and 1e-8."""
     import numpy as np
     import lpgen
     from paper_2601_07628_amd import warmstart as W
@@ -236,6 +237,49 @@ def warmstart_eval(D, torch, n_train=384, n_test=128, epochs=8, lr=1e-3, eps_lis
                                      for c in ("both", "primal", "dual", "cold")}}
         out[f"eps_{eps:g}"] = row
         log(f"warm start eps={eps:g}: {row}")
+    net.close()
+    G.close()
+    return out
+
+
+def warmstart_small_family(D, torch):
+    """The learned warm start on a family where the start matters: a
+    constructed LP of 1,500 rows and 3,000 columns (8 nonzeros per column)
+    and 36 members perturbed as the config-4 family (lognormal sigma 0.1 on
+    b and c); 28 train (FP64 targets to 1e-8, 12 epochs of Adam), 8 are held
+    out and solved to 1e-8 cold, from the family mean and from the network
+    (trial-judged, the trial iterations and time counted)."""
+    import numpy as np
+    import lpgen
+    from paper_2601_07628_amd import warmstart as W
+    s = torch.cuda.current_stream()
+    base = lpgen.constructed_lp(1500, 3000, 750, 8, seed=21)
+    insts = [lpgen.perturbed(base, 1000 + 21 * 100 + i) for i in range(36)]
+    train_i, test_i = insts[:28], insts[28:]
+    G = D.Problem(base, gpu_params(D, eps=1e-8), stream=s)
+    sols = W.family_targets(G, train_i)
+    ref = W.reference(train_i, sols)
+    net = D.WarmStartNet(G, layers=3, stream=s)
+    net.set_params(W.init_params(3, seed=2))
+    net.set_reference(*ref)
+    t0 = time.perf_counter()
+    hist = W.train(net, train_i, sols, epochs=12, lr=3e-3)
+    torch.cuda.synchronize()
+    out = {"family": "constructed LP m=1500, n=3000, 24,000 nonzeros; 28 training and 8 "
+                     "held-out members (lognormal sigma 0.1 on b and c)",
+           "targets_converged": int(sum(x is not None for x in sols)),
+           "train_seconds": round(time.perf_counter() - t0, 2),
+           "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    row = {}
+    for mode in ("cold", "mean", "gnn"):
+        rs = [W.warm_solve(G, inst, mode, net=net, ref=ref) for inst in test_i]
+        row[mode] = {"mean_iters": round(float(np.mean([r["iters"] for r in rs])), 1),
+                     "mean_ms": round(1e3 * float(np.mean([r["seconds"] for r in rs])), 3),
+                     "converged": int(sum(r["status"] == D.CONVERGED for r in rs)),
+                     "fallbacks": int(sum(r["fallback"] for r in rs)),
+                     "per_member_iters": [int(r["iters"]) for r in rs]}
+    out["eps_1e-08"] = row
+    log(f"warm start, small family: { {m: (v['mean_iters'], v['mean_ms']) for m, v in row.items()} }")
     net.close()
     G.close()
     return out
@@ -823,6 +867,8 @@ def main():
         guarded("lasso_qp_fp64", lasso)
         if not args.no_warmstart:
             guarded("warm_start_c4", ws)
+            guarded("warm_start_small_family", lambda: extra.__setitem__(
+                "warm_start_small_family", warmstart_small_family(D, torch)))
 
     def cost_model():
         # the paper's per-iteration model (App. E) with MI355X constants, for
