@@ -118,8 +118,10 @@ typedef struct dpdlp_params {
                               /* its gathered vector exceeds 4 MB, when the  */
                               /* gathers of one XCD's resident tiles (160    */
                               /* consecutive tiles) touch more than 2 MB of  */
-                              /* it, and when its partial sums, one per      */
-                              /* (segment, slice) with nonzeros at 20 bytes  */
+                              /* it (128-byte lines of 8-byte entries, in    */
+                              /* both precisions), and when its partial      */
+                              /* sums, one per (segment, slice) with         */
+                              /* nonzeros at 20 bytes                        */
                               /* each, cost less than its 12 bytes per       */
                               /* nonzero: S = 16 when 8 slices would exceed  */
                               /* 2 MB each (in the iterate's precision) and  */

@@ -1092,9 +1092,12 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
         auto pick = [&](const hvec<int32_t> &ptr, const hvec<int32_t> &idx,
                         const hvec<int32_t> &gptr, int32_t nseg, int32_t nidx) -> int {
             if (8.0 * nidx <= l2) return 0;
+            // (the footprint is measured with FP64 entries, 16 per line, in
+            // both precisions: an FP32 footprint is smaller only where
+            // consecutive entries are gathered, and slicing such a step
+            // still pays in FP32 - on c2's dual step 0.109 ms unsliced)
             const int64_t window = (int64_t)32 * 5 * P->prm.tile_nnz;
-            if (gather_window_bytes(idx, nnz, nidx, window, (int32_t)(128 / eb), 16) <= l2 / 2)
-                return 0;
+            if (gather_window_bytes(idx, nnz, nidx, window, 16, 16) <= l2 / 2) return 0;
             // 16 slices when 8 would leave more than half an L2 per slice and
             // each gathered element is read at least 4 times per pass
             int S = (eb * nidx / 8.0 > l2 / 2 && (double)nnz >= 4.0 * nidx) ? 16 : 8;
