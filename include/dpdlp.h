@@ -45,6 +45,9 @@ extern "C" {
 #define DPDLP_TIME_LIMIT       3
 #define DPDLP_NUMERICAL        4   /* a NaN/Inf appeared in the iterate        */
 
+/* Where the pointers of a call live.  Every call that takes a memory kind
+ * (in its arguments or in dpdlp_csr_lp) rejects any other value with
+ * DPDLP_E_INVALID_ARG before it reads a pointer.                          */
 #define DPDLP_MEM_HOST         0
 #define DPDLP_MEM_DEVICE       1
 

@@ -679,6 +679,7 @@ int dpdlp_gnn_set_reference(dpdlp_gnn *G, const double *c_ref, const double *b_r
                             const double *x_ref, const double *y_ref, int32_t mem_kind, void *stream)
 {
     if (!G || !c_ref || !b_ref || !x_ref || !y_ref) { set_error("NULL argument"); return DPDLP_E_INVALID_ARG; }
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     G->s = (hipStream_t)stream;
     const long m = G->pv.m, n = G->pv.n;
     const int k = mem_kind == DPDLP_MEM_HOST ? (int)hipMemcpyHostToDevice : (int)hipMemcpyDeviceToDevice;
@@ -695,6 +696,7 @@ int dpdlp_gnn_set_instance(dpdlp_gnn *G, const double *c, const double *con_lo, 
                            int32_t mem_kind, void *stream)
 {
     if (!G || !c || !con_lo || !con_hi) { set_error("NULL argument"); return DPDLP_E_INVALID_ARG; }
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     if (!G->have_ref) { set_error("dpdlp_gnn_set_reference first"); return DPDLP_E_INVALID_ARG; }
     G->s = (hipStream_t)stream;
     const int m = G->pv.m, n = G->pv.n;
@@ -715,6 +717,7 @@ int dpdlp_gnn_set_instance(dpdlp_gnn *G, const double *c, const double *con_lo, 
 int dpdlp_gnn_forward(dpdlp_gnn *G, double *x0, double *y0, int32_t mem_kind, void *stream)
 {
     if (!G) { set_error("NULL argument"); return DPDLP_E_INVALID_ARG; }
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     if (!G->have_inst) { set_error("dpdlp_gnn_set_instance first"); return DPDLP_E_INVALID_ARG; }
     G->s = (hipStream_t)stream;
     const int m = G->pv.m, n = G->pv.n;
@@ -742,6 +745,7 @@ int dpdlp_gnn_backward(dpdlp_gnn *G, const double *x_target, const double *y_tar
                        double *loss2, void *stream)
 {
     if (!G || !x_target || !y_target) { set_error("NULL argument"); return DPDLP_E_INVALID_ARG; }
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     if (!G->have_inst) { set_error("dpdlp_gnn_set_instance first"); return DPDLP_E_INVALID_ARG; }
     G->s = (hipStream_t)stream;
     const int m = G->pv.m, n = G->pv.n;

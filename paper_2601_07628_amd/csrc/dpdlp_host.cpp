@@ -18,6 +18,12 @@ namespace dpdlp {
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
+int bad_mem_kind()
+{
+    set_error("mem_kind must be DPDLP_MEM_HOST (0) or DPDLP_MEM_DEVICE (1)");
+    return DPDLP_E_INVALID_ARG;
+}
+
 int validate_host(const dpdlp_csr_lp *lp)
 {
     if (!lp) { set_error("lp is NULL"); return DPDLP_E_INVALID_ARG; }

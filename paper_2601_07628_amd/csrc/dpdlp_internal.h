@@ -94,6 +94,11 @@ constexpr int kMaxSegs = DPDLP_TILE_SEGS_MAX;     // segments per tile
 
 void set_error(const std::string &msg);
 
+// The two memory kinds of the C ABI.  Any other value is rejected before a
+// pointer is touched (a host pointer read as device memory would fault).
+inline bool mem_kind_ok(int32_t k) { return k == DPDLP_MEM_HOST || k == DPDLP_MEM_DEVICE; }
+int bad_mem_kind();     // sets the message, returns DPDLP_E_INVALID_ARG
+
 // Host copy of an LP after the block permutation, with both formats.
 struct HostMatrix {
     int32_t m = 0, n = 0;

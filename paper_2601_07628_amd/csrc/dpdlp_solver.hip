@@ -990,6 +990,7 @@ static int create_impl(const dpdlp_csr_lp *lp_in, const dpdlp_params *params, vo
     auto t_start = std::chrono::steady_clock::now();
     if (!lp_in || !out) { set_error("NULL argument"); return DPDLP_E_INVALID_ARG; }
     *out = nullptr;
+    if (!mem_kind_ok(lp_in->mem_kind)) return bad_mem_kind();
     // Host copy of the input (device inputs are brought over for the integer
     // preprocessing).
     dpdlp_csr_lp lp = *lp_in;
@@ -1471,6 +1472,7 @@ int dpdlp_problem_update_data(dpdlp_problem *P, const double *c, const double *c
                               int32_t mem_kind, void *stream)
 {
     ENTER(P);
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     const int32_t m = P->m, n = P->n;
     struct Item { const double *src; int k; const std::vector<int32_t> *perm; double *dst; } items[] = {
         {c, n, &P->h_perm_col, P->c0}, {var_lo, n, &P->h_perm_col, P->vlo0},
@@ -1602,6 +1604,7 @@ int dpdlp_set_objective_diag(dpdlp_problem *P, const double *q, int32_t mem_kind
 int dpdlp_init(dpdlp_problem *P, const double *x0, const double *y0, int32_t mem_kind, void *stream)
 {
     ENTER(P);
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     return init_impl(P, x0, y0, mem_kind);
 }
 
@@ -1616,6 +1619,7 @@ int dpdlp_solve(dpdlp_problem *P, const double *x0, const double *y0, double *x_
                 double *y_out, int32_t mem_kind, dpdlp_result *info, void *stream)
 {
     ENTER(P);
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     CHK(init_impl(P, x0, y0, mem_kind));
     CHK(iterate_impl(P, P->prm.max_iters));
     CHK(output_impl(P, x_out, y_out, mem_kind));
@@ -1627,6 +1631,7 @@ int dpdlp_get_result(dpdlp_problem *P, double *x_out, double *y_out, int32_t mem
                      dpdlp_result *info, void *stream)
 {
     ENTER(P);
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     CHK(output_impl(P, x_out, y_out, mem_kind));
     fill_result(P, info);
     return DPDLP_OK;
@@ -1636,6 +1641,7 @@ int dpdlp_state_export(dpdlp_problem *P, dpdlp_state *st, double *x, double *y, 
                        double *ya, double *xh, double *yh, int32_t mem_kind, void *stream)
 {
     ENTER(P);
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     const int32_t m = P->m, n = P->n;
     struct Item { double *dst; int isx; const double *src64; const float *src32; } items[] = {
         {x, 1, P->x, P->x32}, {y, 0, P->y, P->y32}, {xa, 1, P->xa, P->xa32},
@@ -1673,6 +1679,7 @@ int dpdlp_state_import(dpdlp_problem *P, const dpdlp_state *st, const double *x,
 {
     ENTER(P);
     if (!st || !x || !y || !xa || !ya) { set_error("state import needs st, x, y, xa, ya"); return DPDLP_E_INVALID_ARG; }
+    if (!mem_kind_ok(mem_kind)) return bad_mem_kind();
     if (P->prm.precision == DPDLP_FP32_MIXED) { set_error("state import is FP64 only"); return DPDLP_E_NOT_SUPPORTED; }
     const int32_t m = P->m, n = P->n;
     struct Item { const double *src; int isx; double *dst; } items[] = {
@@ -1740,6 +1747,7 @@ int dpdlp_kkt(dpdlp_problem *P, const double *x, const double *y, double tau, in
 {
     ENTER(P);
     if (!out5 || (!x) != (!y)) { set_error("bad arguments"); return DPDLP_E_INVALID_ARG; }
+    if (x && !mem_kind_ok(mem_kind)) return bad_mem_kind();
     const int32_t m = P->m, n = P->n;
     if (tau <= 0) tau = P->eta / P->omega;
     if (!x) {

@@ -628,3 +628,38 @@ def test_time_gather_probe(D):
         with pytest.raises(D.DpdlpError, match="dpdlp_time_gather") as e:
             D.dpdlp_time_gather(**bad)
         assert e.value.code == D.E_INVALID_ARG
+
+
+def test_bad_memory_kind_is_rejected_before_any_pointer_is_read(D):
+    """A memory kind other than host (0) or device (1) is an INVALID_ARG
+    error at every entry point that takes one, raised before a pointer is
+    read, so host arrays passed with a wrong kind cannot fault the GPU."""
+    import ctypes as C
+    lp = lpgen.config0()
+    arrs = D.host_arrays(lp)
+    bad = 7
+    out = C.c_void_p()
+    rc = D._lib.dpdlp_problem_create(C.byref(D._csr_struct(arrs, lp.m, lp.n, bad)),
+                                     C.byref(gpu_params(D)), None, C.byref(out))
+    assert rc == D.E_INVALID_ARG and "mem_kind" in D.dpdlp_last_error()
+    G = D.Problem(lp, gpu_params(D))
+    x, y = np.zeros(lp.n), np.zeros(lp.m)
+    k = np.zeros(5)
+    res = D.Result()
+    calls = {
+        "init": lambda: D._lib.dpdlp_init(G.h, x.ctypes.data, y.ctypes.data, bad, None),
+        "solve": lambda: D._lib.dpdlp_solve(G.h, None, None, x.ctypes.data, y.ctypes.data, bad,
+                                            C.byref(res), None),
+        "get_result": lambda: D._lib.dpdlp_get_result(G.h, x.ctypes.data, y.ctypes.data, bad,
+                                                      C.byref(res), None),
+        "kkt": lambda: D._lib.dpdlp_kkt(G.h, x.ctypes.data, y.ctypes.data, 1.0, bad,
+                                        k.ctypes.data, None),
+        "update_data": lambda: D._lib.dpdlp_problem_update_data(G.h, arrs["c"].ctypes.data, None,
+                                                                None, None, None, bad, None),
+    }
+    for name, call in calls.items():
+        assert call() == D.E_INVALID_ARG, name
+        assert "mem_kind" in D.dpdlp_last_error(), name
+    # the handle still works afterwards
+    r = G.solve()
+    assert r["status"] == D.CONVERGED
