@@ -140,6 +140,9 @@ def test_c2_solves_to_1e8_at_the_oracle_objective(D, precision):
     r = G.solve()
     assert r["status"] == D.CONVERGED
     assert max(r["r_primal"], r["r_dual"], r["r_gap"]) <= 1e-8
+    # the automatic rule slices the dual step (x-bar, 72 MB) in both
+    # precisions and leaves the primal step (y, 48 KB) unsliced
+    assert (r["slices_primal"], r["slices_dual"]) == (0, 8)
     err = abs(r["obj_primal"] - ref["obj_primal"]) / (1 + abs(ref["obj_primal"]))
     print(f"c2 {precision}: {r['iters']} iterations ({r['fp32_iters']} in FP32), objective "
           f"{r['obj_primal']:.10g} against the oracle's {ref['obj_primal']:.10g} "
