@@ -183,18 +183,20 @@ def test_c1_solves_to_1e4_at_the_oracle_objective(D, precision):
     assert err <= 10 * 1e-4, err
 
 
-def test_lasso_qp_fullsize_fp32_mixed_against_fp64_oracle(D):
-    """The LASSO QP at full size in the FP32-mixed form, held in FP32, against
-    the FP64 oracle over the same 70 iterations: the same restart decisions
-    and T(z) within 1e-5 relative, the bar of the c3 test (FP32 rounding of
-    A~, the iterates and the sums, about 6e-8 per operation)."""
-    lp, eta, w0, st = _oracle_run("lasso", 70)
-    G, gs = _gpu_run(D, lp, eta, w0, 70, gather_slices=-1, precision=D.FP32_MIXED,
+@pytest.mark.parametrize("name,n_iters", [("lasso", 70), ("c2", 100)])
+def test_fullsize_fp32_mixed_against_fp64_oracle(D, name, n_iters):
+    """The LASSO QP and c2 at full size in the FP32-mixed form, held in FP32
+    (c2's dual step sliced, as in FP64), against the FP64 oracle over the
+    iterations of their FP64 parity tests: the same restart decisions and
+    T(z) within 1e-5 relative, the bar of the c3 test (FP32 rounding of A~,
+    the iterates and the sums, about 6e-8 per operation)."""
+    lp, eta, w0, st = _oracle_run(name, n_iters)
+    G, gs = _gpu_run(D, lp, eta, w0, n_iters, gather_slices=-1, precision=D.FP32_MIXED,
                      fp32_switch_tol=0.0, fp32_stall_checks=10**6, fp32_diverge=0.0)
-    assert G.result(want_xy=False)["fp32_iters"] == 70
+    assert G.result(want_xy=False)["fp32_iters"] == n_iters
     lg, lo = G.log(), st["log"]
     assert [(e["t"], e["k"], e["restart"]) for e in lg] == \
         [(e["t"], e["k"], e["restart"]) for e in lo]
     errs = {k: rel(gs[k], st[k]) for k in ("xh", "yh")}
-    print(f"LASSO QP (FP32-mixed) vs FP64 oracle after 70 iterations: {errs}")
+    print(f"{name} (FP32-mixed) vs FP64 oracle after {n_iters} iterations: {errs}")
     assert max(errs.values()) <= 1e-5, errs
