@@ -37,7 +37,7 @@ def _oracle_run(name, n_iters):
     """The oracle's first n_iters iterations on a benchmark workload, with
     the step size from a short power estimate (kept for the next test)."""
     import oracle
-    lp = {"c1": lpgen.config1, "c2": lpgen.config2,
+    lp = {"c1": lpgen.config1, "c2": lpgen.config2, "staircase": lpgen.config1_staircase,
           "lasso": lambda: lpgen.lasso_qp(1_000_000, 500_000, 20, seed=7)}[name]()
     P0 = oracle.Problem(lp, oracle.Params(eta=1.0, omega0=0.0, eps=0.0))
     sig, _ = P0.sigma_max_power(max_iters=8, tol=0.0)
@@ -105,6 +105,12 @@ def test_c3_fullsize_fp32_mixed_against_fp64_oracle(D):
           f"KKT values within {max(kkt):.2e} relative")
     assert max(errs.values()) <= 1e-5, errs
     assert max(kkt) <= 1e-2
+
+
+def test_staircase_fullsize_parity(D):
+    """The 40M-nonzero staircase LP that bench.py solves to 1e-8: 140
+    iterations with the default parameters (its dual step sliced)."""
+    _fullsize(D, "staircase", 140, -1)
 
 
 def test_c2_fullsize_parity(D):
