@@ -479,6 +479,10 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark, run the permutation x partition "
                          "ablation on config 1 and its staircase variant")
+    ap.add_argument("--gather-sweep", action="store_true",
+                    help="instead of the benchmark, measure the random-gather rate "
+                         "(dpdlp_time_gather, 40M gathers) over the slice size, in FP64 "
+                         "and FP32, with 8 and 16 slices")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
@@ -537,6 +541,24 @@ def main():
             Gt.close()
         print(json.dumps({"c1_time_to_tol": args.c1_tol, "cap_s": args.c1_cap,
                           "kernel_source": kernel_source_hash(), "result": res}), flush=True)
+        return
+
+    if args.gather_sweep:
+        rows = []
+        for prec, eb in ((D.FP64, 8), (D.FP32_MIXED, 4)):
+            for S in (8, 16):
+                for nv in [1 << k for k in range(17, 25)]:
+                    r = D.dpdlp_time_gather(nv, S, 40_000_000, precision=prec, reps=10,
+                                            stream=stream)
+                    rows.append({"precision": "fp64" if prec == D.FP64 else "fp32",
+                                 "slices": S, "n_vec": nv,
+                                 "MB_per_slice": round(nv * eb / S / 2 ** 20, 4),
+                                 "avg_ms": round(r["avg_ms"], 5),
+                                 "Ggathers_per_s": round(r["gathers_per_s"] / 1e9, 1)})
+                    log(f"gather sweep: {rows[-1]}")
+        print(json.dumps({"gather_sweep": "40M uniform random gathers, 2048 per workgroup, "
+                                          "each workgroup inside one slice, slice s on XCD s % 8",
+                          "kernel_source": kernel_source_hash(), "rows": rows}), flush=True)
         return
 
     if args.ablation:
