@@ -372,6 +372,29 @@ def test_matrix_without_nonzeros(D, O):
 
 
 @pytest.mark.parametrize("slices", [-1, 8])
+def test_row_split_into_hundreds_of_pieces(D, O, slices):
+    """One dense row of 300,000 nonzeros (147 pieces of 2048, or about 18 per
+    slice when sliced) above 2,000 short rows: the pieces' carries are added
+    in piece order by k_split_fix."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(13)
+    n, m_short = 300_000, 2000
+    dense = sp.csr_matrix(rng.uniform(0.5, 1.5, (1, n)))
+    short = sp.random(m_short, n, density=4.0 / n, random_state=14, format="csr",
+                      data_rvs=lambda k: rng.standard_normal(k))
+    A = sp.vstack([dense, short]).tocsr()
+    A.sort_indices()
+    x0 = rng.uniform(0.0, 1.0, n)
+    b = A @ x0
+    lo = np.concatenate([[-np.inf], b[1:] - 0.5])
+    hi = np.concatenate([[b[0] + 1.0], b[1:] + 0.5])
+    lp = lpgen.LP(A.shape[0], n, A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                  A.data.copy(), rng.standard_normal(n), lo, hi, np.zeros(n), np.ones(n),
+                  name="long-row")
+    fixed_run(D, O, lp, 200, gpu_kw=dict(gather_slices=slices))
+
+
+@pytest.mark.parametrize("slices", [-1, 8])
 def test_single_row_and_single_column(D, O, slices):
     """One row of 5000 nonzeros and one column of 4000 (split over tiles;
     sliced: split within a slice, and 1-wide index ranges)."""
