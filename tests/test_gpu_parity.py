@@ -371,26 +371,31 @@ def test_matrix_without_nonzeros(D, O):
     assert abs(r["obj_primal"] - np.sum(np.where(c > 0, c * lo, c * hi))) <= 1e-9
 
 
-@pytest.mark.parametrize("slices", [-1, 8])
-def test_row_split_into_hundreds_of_pieces(D, O, slices):
-    """One dense row of 300,000 nonzeros (147 pieces of 2048, or about 18 per
-    slice when sliced) above 2,000 short rows: the pieces' carries are added
-    in piece order by k_split_fix."""
+@pytest.mark.parametrize("orient,slices", [("row", 8), ("column", -1)])
+def test_segment_split_into_hundreds_of_pieces(D, O, orient, slices):
+    """One dense row (dual step) or column (primal step) of 300,000 nonzeros
+    (147 pieces of 2048, or about 18 per slice when sliced) beside 2,000
+    short ones: the pieces' carries are added in piece order by
+    k_split_fix."""
     import scipy.sparse as sp
     rng = np.random.default_rng(13)
-    n, m_short = 300_000, 2000
-    dense = sp.csr_matrix(rng.uniform(0.5, 1.5, (1, n)))
-    short = sp.random(m_short, n, density=4.0 / n, random_state=14, format="csr",
+    big, n_short = 300_000, 2000
+    dense = sp.csr_matrix(rng.uniform(0.5, 1.5, (1, big)))
+    short = sp.random(n_short, big, density=4.0 / big, random_state=14, format="csr",
                       data_rvs=lambda k: rng.standard_normal(k))
     A = sp.vstack([dense, short]).tocsr()
+    if orient == "column":
+        A = A.T.tocsr()
     A.sort_indices()
+    m, n = A.shape
     x0 = rng.uniform(0.0, 1.0, n)
     b = A @ x0
-    lo = np.concatenate([[-np.inf], b[1:] - 0.5])
-    hi = np.concatenate([[b[0] + 1.0], b[1:] + 0.5])
-    lp = lpgen.LP(A.shape[0], n, A.indptr.astype(np.int32), A.indices.astype(np.int32),
+    lo, hi = b - 0.5, b + 0.5
+    if orient == "row":
+        lo[0], hi[0] = -np.inf, b[0] + 1.0
+    lp = lpgen.LP(m, n, A.indptr.astype(np.int32), A.indices.astype(np.int32),
                   A.data.copy(), rng.standard_normal(n), lo, hi, np.zeros(n), np.ones(n),
-                  name="long-row")
+                  name=f"long-{orient}")
     fixed_run(D, O, lp, 200, gpu_kw=dict(gather_slices=slices))
 
 
